@@ -1,0 +1,180 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) reactive capillary-infiltration
+ * lattice Boltzmann library.
+ *
+ * The library advances the 2D lattice Boltzmann model of Sergi, Grossi,
+ * Leidi & Ortona, "Lattice Boltzmann simulation of the surface growth effects
+ * for the infiltration of molten Si in carbon preforms" (section "LB models"):
+ * two fluid components (wetting Si and the other substance) on a D2Q9 BGK
+ * lattice with bounce-back at the solid phase, fluid-fluid cohesion and
+ * solid-fluid adhesion forces, a D2Q5 BGK lattice for the dissolved species
+ * weakly coupled to the flow, and surface reaction by mass precipitation
+ * with rate constant k_r: the precipitated mass accumulates at wall-adjacent
+ * nodes and a node whose mass exceeds a threshold turns solid.  The
+ * observables are the centreline position of the invading front z(t)
+ * (Results, Eq. (1) and Fig. 2), the largest grown solid width Delta e and
+ * pore closure (Fig. 3).
+ *
+ * Conventions for every call:
+ *   - Every call returns lbm_status; nothing throws across the ABI.  On an
+ *     error lbm_last_error() returns a message for the calling thread.
+ *   - Lattice nx*ny nodes, node index y*nx + x, periodic in x and y; walls
+ *     exist only through the solid mask.  Host arrays are row-major (ny, nx).
+ *   - Host inputs are copied before the call returns.
+ *   - `stream` (a hipStream_t) and `workspace` (device memory) are borrowed:
+ *     the caller keeps both alive until lbm_destroy.  All device work of a
+ *     handle is queued on that stream.
+ *   - lbm_step only queues work.  Faults of queued kernels surface at the
+ *     next synchronising call (lbm_observe, lbm_fields, lbm_events,
+ *     lbm_save), which returns LBM_EDEVICE.
+ *   - A handle is used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument, parameter, mask value or buffer size */
+  LBM_ENOMEM = -2,     /* host allocation failed */
+  LBM_EDEVICE = -3,    /* a HIP call or a queued kernel failed */
+  LBM_ENONFINITE = -4, /* a density or concentration is NaN/Inf: handle poisoned */
+  LBM_ESTATE = -5      /* handle poisoned by an earlier LBM_ENONFINITE/LBM_EDEVICE */
+} lbm_status;
+
+typedef struct lbm_sim lbm_sim; /* opaque; owned by the library until lbm_destroy */
+
+/* Model and run parameters.  Readings of the paper that fix these forms are
+ * stated per field. */
+typedef struct {
+  int32_t nx, ny;    /* lattice size, both >= 3 */
+  double tau;        /* flow BGK relaxation time of both components, > 1/2 */
+  double G;          /* cohesion between unlike components (Shan-Chen/Martys-Chen
+                        type: F_s = -G rho_s sum_i w_i rho_other(x+e_i) e_i) */
+  double G_ads[2];   /* adhesion of component 1 (wetting, negative = attracted
+                        to the wall) and 2: F_s -= G_ads[s] rho_s sum_i w_i s(x+e_i) e_i */
+  double tau_g;      /* D2Q5 solute relaxation time, D = (tau_g - 1/2)/3;
+                        0 switches the solute lattice off, else > 1/2 */
+  double k_r;        /* reaction-rate constant [lu/ts]: a fluid node with n_s solid
+                        axis neighbours loses r = k_r n_s phi of its solute per step
+                        (phi = rho1/(rho1+rho2)) to the precipitate; 0 = off.
+                        Requires 0 <= 4 k_r <= 1 and tau_g > 0 when non-zero. */
+  double threshold;  /* precipitated mass above which (strictly) a node turns solid, > 0 */
+  double accel[2];   /* uniform body acceleration on both components (tests) */
+  int32_t x_in, x_out, y0, W; /* capillary for the observables: section
+                        x_in <= x < x_out, channel rows y0..y0+W-1; W = 0: none */
+} lbm_params;
+
+/* Observables of the current state (lbm_observe).  Sums are FP64. */
+typedef struct {
+  int64_t step;              /* number of steps taken since lbm_init */
+  double mass[2];            /* sum of rho_1, rho_2 over fluid nodes */
+  double mass_removed[2];    /* fluid mass taken out by nodes that turned solid */
+  double solute;             /* sum of the solute concentration over fluid nodes */
+  double precipitate;        /* sum of precipitated mass over all nodes */
+  double solute_removed;     /* solute taken out by nodes that turned solid */
+  double front_z;            /* centreline front measured from x_in [lu]; NaN if W == 0;
+                                x_out - x_in if no crossing (breakthrough) */
+  double delta_e;            /* largest solid width grown from one channel wall;
+                                W/2 for a closed column */
+  int64_t closure_step;      /* first step with a closed capillary column, -1 if none */
+  int64_t n_solid;           /* number of solid nodes */
+  int64_t n_events;          /* number of growth events so far */
+  int32_t nonfinite;         /* 1 if any fluid density/concentration is NaN/Inf */
+  int32_t pad;
+} lbm_obs;
+
+/* A growth event: node (x, y) is solid from state `step` on. */
+typedef struct {
+  int32_t x, y;
+  int64_t step;
+} lbm_event;
+
+/* Field selection for lbm_fields; host_fields receives one nx*ny double array
+ * per selected field, in this bit order. */
+enum {
+  LBM_FIELD_RHO1 = 1u << 0,
+  LBM_FIELD_RHO2 = 1u << 1,
+  LBM_FIELD_UX = 1u << 2,   /* barycentric velocity (sum_s j_s + F_s/2)/(rho1+rho2) */
+  LBM_FIELD_UY = 1u << 3,
+  LBM_FIELD_CONC = 1u << 4,
+  LBM_FIELD_PRECIP = 1u << 5,
+  LBM_FIELD_SOLID = 1u << 6 /* 0/1 */
+};
+
+/* Device memory needed by lbm_init for these parameters (bytes). */
+lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Create a simulation.  solid: host nx*ny bytes, values 0/1.  rho1, rho2: host
+ * nx*ny FP64 densities (>= 0, finite; ignored at solid nodes), rounded once to
+ * FP32.  conc: host nx*ny FP64 solute concentration, or NULL when tau_g == 0.
+ * The initial populations are the rest equilibria f_i = w_i rho, g_k = w_k C.
+ * workspace: device buffer of at least lbm_workspace_bytes, 256-byte aligned.
+ * LBM_EINVAL on any bad argument (see the lbm_params fields). */
+lbm_status lbm_init(const lbm_params* p, const uint8_t* solid, const double* rho1,
+                    const double* rho2, const double* conc, void* stream, void* workspace,
+                    size_t ws_bytes, lbm_sim** out);
+
+/* Queue nsteps time steps (nsteps >= 0).  One step: moments, cohesion and
+ * adhesion forces, BGK collision of both components, solute BGK, surface
+ * reaction, streaming with halfway bounce-back, and growth of every node
+ * whose precipitate exceeds the threshold (synchronous, end of step). */
+lbm_status lbm_step(lbm_sim* sim, int64_t nsteps);
+
+/* Observables of the current state.  Synchronises the stream.
+ * LBM_ENONFINITE (and a poisoned handle) if a NaN/Inf is found. */
+lbm_status lbm_observe(lbm_sim* sim, lbm_obs* out);
+
+/* Copy selected macroscopic fields of the current state to the host as FP64
+ * (host_fields: popcount(field_mask) * nx*ny doubles).  Synchronises. */
+lbm_status lbm_fields(lbm_sim* sim, uint32_t field_mask, double* host_fields);
+
+/* Copy growth events [first, first+cap) to buf; *n receives the total count.
+ * Events are unordered within a step.  Synchronises. */
+lbm_status lbm_events(lbm_sim* sim, int64_t first, lbm_event* buf, int64_t cap, int64_t* n);
+
+/* Checkpoint: serialise the whole state (populations, mask, precipitate,
+ * ledgers, events, step) into blob.  With blob == NULL only *n is set to the
+ * size needed.  lbm_load restores a blob written by lbm_save for a handle with
+ * the same parameters; it also clears a poisoned state.  Blob layout (native
+ * endianness, no padding): header {uint64 magic 0x4C424D5853494D31, int32 nx,
+ * ny, int32 flags (1 solute, 2 reaction), int32 version 1, int64 step,
+ * int64 n_events}, then f float[18][N] (component-major, link order e0..e8 =
+ * (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)), g float[5][N]
+ * if solute, mask uint8[N] (bit0 solid, bit1/bit2 growth pending), then if
+ * reaction: m double[N], solid step int32[N] (-1 fluid), removed float[3][N],
+ * events lbm_event[n_events]. */
+lbm_status lbm_save(lbm_sim* sim, void* blob, size_t cap, size_t* n);
+lbm_status lbm_load(lbm_sim* sim, const void* blob, size_t n);
+
+/* Launch shape of the fused step: tx threads per workgroup (64, 128 or 256)
+ * covering tx-2 owned columns, sy owned rows per workgroup (1..4096).
+ * The shape changes no result bit. */
+lbm_status lbm_set_tile(lbm_sim* sim, int32_t tx, int32_t sy);
+lbm_status lbm_get_tile(const lbm_sim* sim, int32_t* tx, int32_t* sy);
+
+/* Arithmetic precision of the step: 64 (default) or 32 bits.  Populations
+ * are stored as FP32 either way; 64 computes moments, forces and the
+ * collision in FP64 from the stored values (the step is bound by memory
+ * traffic, so this costs no time and keeps FP32 rounding to the storage). */
+lbm_status lbm_set_arith(lbm_sim* sim, int32_t bits);
+
+/* Time the launch shapes (steps_per_candidate steps each, on a saved copy of
+ * the state, which is restored), keep the fastest and report it. */
+lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_candidate, int32_t* tx, int32_t* sy,
+                        double* best_ms_per_step);
+
+void lbm_destroy(lbm_sim* sim);
+const char* lbm_strerror(lbm_status s);
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -407,6 +407,34 @@ void orc_step(orc_sim *sim, int64_t n) {
   for (int64_t t = 0; t < n; t++) step_once(sim);
 }
 
+/* Deep copy of a simulation (used to rewind a window when comparing growth
+ * decisions made at two precisions). */
+orc_sim *orc_clone(const orc_sim *src) {
+  orc_sim *sim = alloc_sim(&src->p);
+  if (!sim) return NULL;
+  long N = src->N;
+  memcpy(sim->f, src->f, 18 * N * sizeof(double));
+  memcpy(sim->g, src->g, 5 * N * sizeof(double));
+  memcpy(sim->s, src->s, N);
+  memcpy(sim->m, src->m, N * sizeof(double));
+  memcpy(sim->solid_step, src->solid_step, N * sizeof(int64_t));
+  memcpy(sim->removed, src->removed, sizeof sim->removed);
+  sim->step = src->step;
+  if (src->nev) {
+    sim->ev = (orc_event *)malloc(src->nev * sizeof(orc_event));
+    if (!sim->ev) { orc_destroy(sim); return NULL; }
+    memcpy(sim->ev, src->ev, src->nev * sizeof(orc_event));
+    sim->nev = sim->evcap = src->nev;
+  }
+  if (src->nov) {
+    sim->ov = (orc_forced *)malloc(src->nov * sizeof(orc_forced));
+    if (!sim->ov) { orc_destroy(sim); return NULL; }
+    memcpy(sim->ov, src->ov, src->nov * sizeof(orc_forced));
+    sim->nov = sim->ovcap = src->nov;
+  }
+  return sim;
+}
+
 /* Force the growth decision of node (x, y) at the step that produces state
  * `step` (used when a decision is a certified tie between two precisions). */
 int orc_override(orc_sim *sim, int32_t x, int32_t y, int64_t step, int32_t decision) {

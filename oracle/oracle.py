@@ -69,6 +69,8 @@ def lib():
         L.orc_create_state.restype = P
         L.orc_create_state.argtypes = [C.POINTER(_Params), P, P, P, P]
         L.orc_destroy.argtypes = [P]
+        L.orc_clone.restype = P
+        L.orc_clone.argtypes = [P]
         L.orc_step.argtypes = [P, C.c_int64]
         L.orc_fields.argtypes = [P, P, P, P, P, P, P, P]
         L.orc_forces.argtypes = [P, P, P]
@@ -138,6 +140,15 @@ class Oracle:
         if not h:
             raise ValueError("oracle rejected the parameters or the mask")
         self.h = h
+
+    def clone(self) -> "Oracle":
+        new = object.__new__(Oracle)
+        new.p, new.nx, new.ny, new._keep = self.p, self.nx, self.ny, []
+        h = lib().orc_clone(self.h)
+        if not h:
+            raise MemoryError("oracle clone failed")
+        new.h = h
+        return new
 
     @classmethod
     def from_problem(cls, prob):

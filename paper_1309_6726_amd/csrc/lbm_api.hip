@@ -1,0 +1,562 @@
+// Host side of the C ABI declared in include/lbm.h: parameter checks,
+// workspace layout, launch sequencing on the caller's stream, observe /
+// checkpoint transfers and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_dev.h"
+
+using namespace lbmdev;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHECK(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(LBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint64_t kMagic = 0x4C424D5853494D31ull;  // "LBMXSIM1"
+constexpr int kVersion = 1;
+
+struct Layout {
+  long long N = 0, P = 0, ev_cap = 0;
+  int nblocks = 0;
+  bool solute = false, react = false;
+  size_t f[2] = {0, 0}, g[2] = {0, 0}, mask = 0, m = 0, sstep = 0, drop = 0, ev = 0, evc = 0,
+         partial = 0, out = 0, total = 0;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const lbm_params& p) {
+  Layout L;
+  L.N = (long long)p.nx * p.ny;
+  L.P = (L.N + 63) / 64 * 64;
+  L.solute = p.tau_g > 0.0;
+  L.react = p.k_r > 0.0;
+  L.ev_cap = L.react ? L.N : 0;
+  L.nblocks = (int)std::min<long long>(1024, (L.N + 255) / 256);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = a256(off + bytes);
+    return o;
+  };
+  L.f[0] = take(18 * L.P * sizeof(float));
+  L.f[1] = take(18 * L.P * sizeof(float));
+  if (L.solute) {
+    L.g[0] = take(5 * L.P * sizeof(float));
+    L.g[1] = take(5 * L.P * sizeof(float));
+  }
+  L.mask = take(L.P);
+  if (L.react) {
+    L.m = take(L.P * sizeof(double));
+    L.sstep = take(L.P * sizeof(int32_t));
+    L.drop = take(3 * L.P * sizeof(float));
+    L.ev = take(L.ev_cap * sizeof(lbm_event));
+  }
+  L.evc = take(sizeof(unsigned long long));
+  L.partial = take((size_t)L.nblocks * OBS_SLOTS * sizeof(double));
+  L.out = take(OBS_OUT * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+lbm_status check_params(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 3 || p->ny < 3) return fail(LBM_EINVAL, "nx, ny must be >= 3");
+  if ((long long)p->nx * p->ny > (1ll << 31) - 1) return fail(LBM_EINVAL, "lattice too large");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 1/2");
+  if (!(p->tau_g == 0.0 || (p->tau_g > 0.5 && std::isfinite(p->tau_g))))
+    return fail(LBM_EINVAL, "tau_g must be 0 or > 1/2");
+  if (!(p->k_r >= 0.0) || 4.0 * p->k_r > 1.0) return fail(LBM_EINVAL, "need 0 <= 4 k_r <= 1");
+  if (p->k_r > 0.0 && p->tau_g == 0.0) return fail(LBM_EINVAL, "reaction needs the solute lattice");
+  if (!(p->threshold > 0.0) || !std::isfinite(p->threshold)) return fail(LBM_EINVAL, "threshold must be > 0");
+  if (!std::isfinite(p->G) || !std::isfinite(p->G_ads[0]) || !std::isfinite(p->G_ads[1]) ||
+      !std::isfinite(p->accel[0]) || !std::isfinite(p->accel[1]))
+    return fail(LBM_EINVAL, "non-finite force parameter");
+  if (p->W < 0) return fail(LBM_EINVAL, "W must be >= 0");
+  if (p->W > 0) {
+    if (p->x_in < 0 || p->x_out > p->nx || p->x_in + 2 > p->x_out)
+      return fail(LBM_EINVAL, "capillary section out of range");
+    if (p->y0 < 0 || p->y0 + p->W > p->ny) return fail(LBM_EINVAL, "capillary rows out of range");
+  }
+  return LBM_OK;
+}
+
+unsigned pending_bit(long long n) { return (n & 1) ? 4u : 2u; }  // bit written by step n
+
+}  // namespace
+
+struct lbm_sim {
+  lbm_params p;
+  Layout L;
+  hipStream_t stream;
+  char* ws;
+  int cur;         // buffer holding the current state
+  long long step;  // current state index
+  int tx, sy;
+  int arith64;     // 1: FP64 arithmetic in the step (storage stays FP32)
+  bool poisoned;
+  float* f(int i) const { return (float*)(ws + L.f[i]); }
+  float* g(int i) const { return L.solute ? (float*)(ws + L.g[i]) : nullptr; }
+  uint8_t* mask() const { return (uint8_t*)(ws + L.mask); }
+  double* m() const { return L.react ? (double*)(ws + L.m) : nullptr; }
+  int32_t* sstep() const { return L.react ? (int32_t*)(ws + L.sstep) : nullptr; }
+  float* drop() const { return L.react ? (float*)(ws + L.drop) : nullptr; }
+  lbm_event* ev() const { return L.react ? (lbm_event*)(ws + L.ev) : nullptr; }
+  unsigned long long* evc() const { return (unsigned long long*)(ws + L.evc); }
+  double* partial() const { return (double*)(ws + L.partial); }
+  double* out() const { return (double*)(ws + L.out); }
+};
+
+namespace {
+
+lbm_status guard(const lbm_sim* s) {
+  if (!s) return fail(LBM_EINVAL, "handle is NULL");
+  if (s->poisoned) return fail(LBM_ESTATE, "handle poisoned by an earlier failure; lbm_load a checkpoint");
+  return LBM_OK;
+}
+
+bool tile_ok(int tx, int sy) { return (tx == 64 || tx == 128 || tx == 256) && sy >= 1 && sy <= 4096; }
+
+void default_tile(const lbm_params& p, int* tx, int* sy) {
+  *tx = p.nx >= 1024 ? 256 : (p.nx >= 256 ? 128 : 64);
+  *sy = 16;
+}
+
+lbm_status queue_steps(lbm_sim* s, long long n) {
+  const lbm_params& p = s->p;
+  StepArgs a{};
+  a.mask = s->mask();
+  a.m = s->m();
+  a.sstep = s->sstep();
+  a.drop = s->drop();
+  a.ev = s->ev();
+  a.ev_count = s->evc();
+  a.ev_cap = s->L.ev_cap;
+  a.P = s->L.P;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.tx_owned = s->tx - 2;
+  a.sy = s->sy;
+  a.nstrips = (p.nx + a.tx_owned - 1) / a.tx_owned;
+  a.nsegs = (p.ny + s->sy - 1) / s->sy;
+  a.remap = ((a.nstrips * a.nsegs) % 8) == 0;
+  a.solute = s->L.solute;
+  a.react = s->L.react;
+  a.omega = (float)(1.0 / p.tau);
+  a.tau = (float)p.tau;
+  a.G = (float)p.G;
+  a.Gads1 = (float)p.G_ads[0];
+  a.Gads2 = (float)p.G_ads[1];
+  a.ax = (float)p.accel[0];
+  a.ay = (float)p.accel[1];
+  a.omega_g = s->L.solute ? (float)(1.0 / p.tau_g) : 0.0f;
+  a.k_r = p.k_r;
+  a.threshold = p.threshold;
+  for (long long t = 0; t < n; ++t) {
+    a.fin = s->f(s->cur);
+    a.fout = s->f(s->cur ^ 1);
+    a.gin = s->g(s->cur);
+    a.gout = s->g(s->cur ^ 1);
+    a.step = s->step;
+    a.bit_prev = pending_bit(s->step - 1);
+    a.bit_cur = pending_bit(s->step);
+    hipError_t e = launch_step(a, s->tx, s->arith64, s->stream);
+    if (e != hipSuccess) {
+      s->poisoned = true;
+      return fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    }
+    s->cur ^= 1;
+    s->step += 1;
+  }
+  return LBM_OK;
+}
+
+size_t blob_size(const lbm_sim* s, long long nev) {
+  const long long N = s->L.N;
+  size_t n = 8 + 4 * 4 + 8 + 8;  // header
+  n += 18 * N * sizeof(float);
+  if (s->L.solute) n += 5 * N * sizeof(float);
+  n += N;
+  if (s->L.react) n += N * (sizeof(double) + sizeof(int32_t) + 3 * sizeof(float)) + nev * sizeof(lbm_event);
+  return n;
+}
+
+lbm_status copy_planes_d2h(char* dst, const char* src_dev, int planes, long long N, long long P,
+                           size_t esz, hipStream_t st) {
+  for (int q = 0; q < planes; ++q)
+    HIPCHECK(hipMemcpyAsync(dst + q * N * esz, src_dev + q * P * esz, N * esz, hipMemcpyDeviceToHost, st));
+  return LBM_OK;
+}
+
+lbm_status copy_planes_h2d(char* dst_dev, const char* src, int planes, long long N, long long P,
+                           size_t esz, hipStream_t st) {
+  for (int q = 0; q < planes; ++q)
+    HIPCHECK(hipMemcpyAsync(dst_dev + q * P * esz, src + q * N * esz, N * esz, hipMemcpyHostToDevice, st));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+const char* lbm_strerror(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of host memory";
+    case LBM_EDEVICE: return "device error";
+    case LBM_ENONFINITE: return "non-finite density or concentration";
+    case LBM_ESTATE: return "handle poisoned by an earlier failure";
+  }
+  return "unknown status";
+}
+
+lbm_status lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
+  lbm_status st = check_params(p);
+  if (st != LBM_OK) return st;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  *bytes = make_layout(*p).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(const lbm_params* p, const uint8_t* solid, const double* rho1,
+                    const double* rho2, const double* conc, void* stream, void* workspace,
+                    size_t ws_bytes, lbm_sim** out) {
+  lbm_status st = check_params(p);
+  if (st != LBM_OK) return st;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!solid || !rho1 || !rho2) return fail(LBM_EINVAL, "solid, rho1, rho2 are required");
+  const bool solute = p->tau_g > 0.0;
+  if (solute && !conc) return fail(LBM_EINVAL, "conc is required when tau_g > 0");
+  Layout L = make_layout(*p);
+  if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace & 255u) != 0) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(LBM_EINVAL, "workspace too small: %zu < %zu", ws_bytes, L.total);
+  const long long N = L.N;
+  for (long long i = 0; i < N; ++i) {
+    if (solid[i] > 1) return fail(LBM_EINVAL, "mask value %d at node %lld", (int)solid[i], i);
+    if (solid[i]) continue;
+    if (!(rho1[i] >= 0.0) || !(rho2[i] >= 0.0) || !std::isfinite(rho1[i]) || !std::isfinite(rho2[i]))
+      return fail(LBM_EINVAL, "density at node %lld must be finite and >= 0", i);
+    if (rho1[i] + rho2[i] <= 0.0) return fail(LBM_EINVAL, "fluid node %lld has zero density", i);
+    if (solute && (!(conc[i] >= 0.0) || !std::isfinite(conc[i])))
+      return fail(LBM_EINVAL, "concentration at node %lld must be finite and >= 0", i);
+  }
+  lbm_sim* s = (lbm_sim*)calloc(1, sizeof(lbm_sim));
+  if (!s) return fail(LBM_ENOMEM, "handle allocation");
+  s->p = *p;
+  s->L = L;
+  s->stream = (hipStream_t)stream;
+  s->ws = (char*)workspace;
+  s->cur = 0;
+  s->step = 0;
+  default_tile(*p, &s->tx, &s->sy);
+  s->arith64 = 1;
+  // stage the FP64 inputs in the second population buffer (72 B per node)
+  char* stage = (char*)s->f(1);
+  hipStream_t hs = s->stream;
+  auto bail = [&](lbm_status e) { free(s); return e; };
+#define CK(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) { fail(LBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); return bail(LBM_EDEVICE); } } while (0)
+  CK(hipMemcpyAsync(stage, rho1, N * sizeof(double), hipMemcpyHostToDevice, hs));
+  CK(hipMemcpyAsync(stage + N * sizeof(double), rho2, N * sizeof(double), hipMemcpyHostToDevice, hs));
+  if (solute) CK(hipMemcpyAsync(stage + 2 * N * sizeof(double), conc, N * sizeof(double), hipMemcpyHostToDevice, hs));
+  CK(hipMemcpyAsync(s->mask(), solid, N, hipMemcpyHostToDevice, hs));
+  CK(hipMemsetAsync(s->evc(), 0, sizeof(unsigned long long), hs));
+  CK(launch_init((const double*)stage, (const double*)(stage + N * sizeof(double)),
+                 solute ? (const double*)(stage + 2 * N * sizeof(double)) : nullptr, s->mask(),
+                 s->f(0), s->g(0), s->m(), s->sstep(), s->drop(), N, L.P, solute, L.react, hs));
+  CK(hipStreamSynchronize(hs));
+#undef CK
+  *out = s;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_sim* s, int64_t nsteps) {
+  lbm_status st = guard(s);
+  if (st != LBM_OK) return st;
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  return queue_steps(s, nsteps);
+}
+
+lbm_status lbm_observe(lbm_sim* s, lbm_obs* o) {
+  lbm_status st = guard(s);
+  if (st != LBM_OK) return st;
+  if (!o) return fail(LBM_EINVAL, "out is NULL");
+  const lbm_params& p = s->p;
+  const unsigned bp = pending_bit(s->step - 1);
+  hipError_t e = launch_observe(s->f(s->cur), s->g(s->cur), s->mask(), s->m(), s->drop(),
+                                s->sstep(), s->L.N, s->L.P, p.nx, bp, s->L.solute, s->L.react,
+                                s->L.nblocks, s->partial(), s->out(), p.x_in, p.x_out, p.y0, p.W,
+                                s->stream);
+  if (e != hipSuccess) { s->poisoned = true; return fail(LBM_EDEVICE, "observe launch: %s", hipGetErrorString(e)); }
+  double h[OBS_OUT];
+  unsigned long long nev = 0;
+  e = hipMemcpyAsync(h, s->out(), sizeof h, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nev, s->evc(), sizeof nev, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) { s->poisoned = true; return fail(LBM_EDEVICE, "observe: %s", hipGetErrorString(e)); }
+  memset(o, 0, sizeof *o);
+  o->step = s->step;
+  o->mass[0] = h[0];
+  o->mass[1] = h[1];
+  o->solute = h[2];
+  o->precipitate = h[3];
+  o->mass_removed[0] = h[4];
+  o->mass_removed[1] = h[5];
+  o->solute_removed = h[6];
+  o->n_solid = (int64_t)h[7];
+  o->nonfinite = h[8] > 0.0;
+  o->n_events = (int64_t)nev;
+  if (p.W > 0) {
+    o->front_z = h[OBS_SLOTS];
+    o->delta_e = h[OBS_SLOTS + 1];
+    o->closure_step = (int64_t)h[OBS_SLOTS + 2];
+  } else {
+    o->front_z = NAN;
+    o->delta_e = 0.0;
+    o->closure_step = -1;
+  }
+  if ((long long)nev > s->L.ev_cap)
+    return fail(LBM_EDEVICE, "event log overflow (%llu > %lld)", nev, s->L.ev_cap);
+  if (o->nonfinite) {
+    s->poisoned = true;
+    return fail(LBM_ENONFINITE, "%lld fluid nodes hold a NaN/Inf at step %lld", (long long)h[8], s->step);
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_sim* s, uint32_t mask, double* host) {
+  lbm_status st = guard(s);
+  if (st != LBM_OK) return st;
+  if (!host && mask) return fail(LBM_EINVAL, "host_fields is NULL");
+  if (mask >> 7) return fail(LBM_EINVAL, "unknown field bits");
+  const lbm_params& p = s->p;
+  const long long N = s->L.N;
+  // staging: the idle population buffer (72 B per node >= 7 doubles per node);
+  // the next step overwrites every fluid slot of it before reading it
+  double* stage = (double*)s->f(s->cur ^ 1);
+  hipError_t e = launch_fields(s->f(s->cur), s->g(s->cur), s->mask(), s->m(), p.nx, p.ny, s->L.P,
+                               pending_bit(s->step - 1), s->L.solute, s->L.react, (float)p.G,
+                               (float)p.G_ads[0], (float)p.G_ads[1], (float)p.accel[0],
+                               (float)p.accel[1], stage, s->stream);
+  int k = 0;
+  for (int b = 0; b < 7 && e == hipSuccess; ++b) {
+    if (!(mask & (1u << b))) continue;
+    e = hipMemcpyAsync(host + (size_t)k * N, stage + (size_t)b * N, N * sizeof(double),
+                       hipMemcpyDeviceToHost, s->stream);
+    ++k;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) { s->poisoned = true; return fail(LBM_EDEVICE, "fields: %s", hipGetErrorString(e)); }
+  return LBM_OK;
+}
+
+lbm_status lbm_events(lbm_sim* s, int64_t first, lbm_event* buf, int64_t cap, int64_t* n) {
+  lbm_status st = guard(s);
+  if (st != LBM_OK) return st;
+  if (!n || first < 0 || cap < 0 || (cap > 0 && !buf)) return fail(LBM_EINVAL, "bad events arguments");
+  unsigned long long nev = 0;
+  HIPCHECK(hipMemcpyAsync(&nev, s->evc(), sizeof nev, hipMemcpyDeviceToHost, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  *n = (int64_t)nev;
+  long long avail = std::min<long long>((long long)nev, s->L.ev_cap) - first;
+  long long k = std::min<long long>(avail, cap);
+  if (k > 0) {
+    HIPCHECK(hipMemcpyAsync(buf, s->ev() + first, k * sizeof(lbm_event), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipStreamSynchronize(s->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_save(lbm_sim* s, void* blob, size_t cap, size_t* n) {
+  if (!s) return fail(LBM_EINVAL, "handle is NULL");
+  if (!n) return fail(LBM_EINVAL, "n is NULL");
+  unsigned long long nev = 0;
+  HIPCHECK(hipMemcpyAsync(&nev, s->evc(), sizeof nev, hipMemcpyDeviceToHost, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  nev = std::min<unsigned long long>(nev, (unsigned long long)s->L.ev_cap);
+  const size_t need = blob_size(s, (long long)nev);
+  *n = need;
+  if (!blob) return LBM_OK;
+  if (cap < need) return fail(LBM_EINVAL, "blob too small: %zu < %zu", cap, need);
+  char* b = (char*)blob;
+  const long long N = s->L.N, P = s->L.P;
+  const int32_t hdr32[4] = {s->p.nx, s->p.ny, (s->L.solute ? 1 : 0) | (s->L.react ? 2 : 0), kVersion};
+  const int64_t step = s->step, nev64 = (int64_t)nev;
+  memcpy(b, &kMagic, 8); b += 8;
+  memcpy(b, hdr32, 16); b += 16;
+  memcpy(b, &step, 8); b += 8;
+  memcpy(b, &nev64, 8); b += 8;
+  lbm_status st;
+  if ((st = copy_planes_d2h(b, (const char*)s->f(s->cur), 18, N, P, 4, s->stream)) != LBM_OK) return st;
+  b += 18 * N * 4;
+  if (s->L.solute) {
+    if ((st = copy_planes_d2h(b, (const char*)s->g(s->cur), 5, N, P, 4, s->stream)) != LBM_OK) return st;
+    b += 5 * N * 4;
+  }
+  HIPCHECK(hipMemcpyAsync(b, s->mask(), N, hipMemcpyDeviceToHost, s->stream));
+  b += N;
+  if (s->L.react) {
+    HIPCHECK(hipMemcpyAsync(b, s->m(), N * 8, hipMemcpyDeviceToHost, s->stream));
+    b += N * 8;
+    HIPCHECK(hipMemcpyAsync(b, s->sstep(), N * 4, hipMemcpyDeviceToHost, s->stream));
+    b += N * 4;
+    if ((st = copy_planes_d2h(b, (const char*)s->drop(), 3, N, P, 4, s->stream)) != LBM_OK) return st;
+    b += 3 * N * 4;
+    if (nev) HIPCHECK(hipMemcpyAsync(b, s->ev(), nev * sizeof(lbm_event), hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_sim* s, const void* blob, size_t n) {
+  if (!s) return fail(LBM_EINVAL, "handle is NULL");
+  if (!blob || n < 40) return fail(LBM_EINVAL, "blob too small");
+  const char* b = (const char*)blob;
+  uint64_t magic;
+  int32_t hdr32[4];
+  int64_t step, nev;
+  memcpy(&magic, b, 8);
+  memcpy(hdr32, b + 8, 16);
+  memcpy(&step, b + 24, 8);
+  memcpy(&nev, b + 32, 8);
+  const int flags = (s->L.solute ? 1 : 0) | (s->L.react ? 2 : 0);
+  if (magic != kMagic || hdr32[3] != kVersion) return fail(LBM_EINVAL, "not a checkpoint of this library");
+  if (hdr32[0] != s->p.nx || hdr32[1] != s->p.ny || hdr32[2] != flags)
+    return fail(LBM_EINVAL, "checkpoint is for another lattice or feature set");
+  if (step < 0 || nev < 0 || nev > s->L.ev_cap) return fail(LBM_EINVAL, "bad checkpoint counters");
+  if (n != blob_size(s, nev)) return fail(LBM_EINVAL, "checkpoint size mismatch");
+  b += 40;
+  const long long N = s->L.N, P = s->L.P;
+  // the mask must hold only bit0 and the pending bit of the last step taken
+  const char* mb = b + 18 * N * 4 + (s->L.solute ? 5 * N * 4 : 0);
+  const unsigned allowed = 1u | pending_bit(step - 1);
+  for (long long i = 0; i < N; ++i)
+    if ((unsigned)(uint8_t)mb[i] & ~allowed) return fail(LBM_EINVAL, "bad mask byte at node %lld", i);
+  lbm_status st;
+  if ((st = copy_planes_h2d((char*)s->f(0), b, 18, N, P, 4, s->stream)) != LBM_OK) return st;
+  b += 18 * N * 4;
+  if (s->L.solute) {
+    if ((st = copy_planes_h2d((char*)s->g(0), b, 5, N, P, 4, s->stream)) != LBM_OK) return st;
+    b += 5 * N * 4;
+  }
+  HIPCHECK(hipMemcpyAsync(s->mask(), b, N, hipMemcpyHostToDevice, s->stream));
+  b += N;
+  unsigned long long nev_u = (unsigned long long)nev;
+  if (s->L.react) {
+    HIPCHECK(hipMemcpyAsync(s->m(), b, N * 8, hipMemcpyHostToDevice, s->stream));
+    b += N * 8;
+    HIPCHECK(hipMemcpyAsync(s->sstep(), b, N * 4, hipMemcpyHostToDevice, s->stream));
+    b += N * 4;
+    if ((st = copy_planes_h2d((char*)s->drop(), b, 3, N, P, 4, s->stream)) != LBM_OK) return st;
+    b += 3 * N * 4;
+    if (nev) HIPCHECK(hipMemcpyAsync(s->ev(), b, nev * sizeof(lbm_event), hipMemcpyHostToDevice, s->stream));
+  }
+  HIPCHECK(hipMemcpyAsync(s->evc(), &nev_u, sizeof nev_u, hipMemcpyHostToDevice, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  s->cur = 0;
+  s->step = step;
+  s->poisoned = false;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_sim* s, int32_t tx, int32_t sy) {
+  if (!s) return fail(LBM_EINVAL, "handle is NULL");
+  if (!tile_ok(tx, sy)) return fail(LBM_EINVAL, "tile %d x %d not supported", tx, sy);
+  s->tx = tx;
+  s->sy = sy;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_arith(lbm_sim* s, int32_t bits) {
+  if (!s) return fail(LBM_EINVAL, "handle is NULL");
+  if (bits != 32 && bits != 64) return fail(LBM_EINVAL, "arithmetic precision must be 32 or 64");
+  s->arith64 = bits == 64;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_tile(const lbm_sim* s, int32_t* tx, int32_t* sy) {
+  if (!s || !tx || !sy) return fail(LBM_EINVAL, "NULL argument");
+  *tx = s->tx;
+  *sy = s->sy;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_out, double* best_ms) {
+  lbm_status st = guard(s);
+  if (st != LBM_OK) return st;
+  if (steps < 1) return fail(LBM_EINVAL, "steps_per_candidate must be >= 1");
+  size_t n = 0;
+  if ((st = lbm_save(s, nullptr, 0, &n)) != LBM_OK) return st;
+  std::vector<char> blob;
+  try { blob.resize(n); } catch (...) { return fail(LBM_ENOMEM, "checkpoint buffer"); }
+  if ((st = lbm_save(s, blob.data(), n, &n)) != LBM_OK) return st;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  const int txs[] = {64, 128, 256};
+  const int sys[] = {4, 8, 16, 32, 64, 128};
+  int btx = s->tx, bsy = s->sy;
+  float best = 1e30f;
+  for (int tx : txs) {
+    if (tx > 2 * s->p.nx + 2 && tx != 64) continue;
+    for (int sy : sys) {
+      if (sy > 2 * s->p.ny && sy != 4) continue;
+      s->tx = tx;
+      s->sy = sy;
+      if ((st = queue_steps(s, 2)) != LBM_OK) break;
+      if (hipEventRecord(e0, s->stream) != hipSuccess) { st = fail(LBM_EDEVICE, "autotune event"); break; }
+      if ((st = queue_steps(s, steps)) != LBM_OK) break;
+      float ms = 0;
+      if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(LBM_EDEVICE, "autotune timing");
+        break;
+      }
+      if (ms < best) { best = ms; btx = tx; bsy = sy; }
+    }
+    if (st != LBM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LBM_OK) return st;
+  if ((st = lbm_load(s, blob.data(), n)) != LBM_OK) return st;
+  s->tx = btx;
+  s->sy = bsy;
+  if (tx_out) *tx_out = btx;
+  if (sy_out) *sy_out = bsy;
+  if (best_ms) *best_ms = best / steps;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_sim* s) { free(s); }
+
+}  // extern "C"
