@@ -12,6 +12,7 @@ growth) over all 4,194,304 nodes.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,14 +35,53 @@ def wall_adjacent(solid: np.ndarray) -> np.ndarray:
     return (~s) & (n > 0)
 
 
-def algorithmic_bytes(solid: np.ndarray, react: bool) -> int:
-    """HBM bytes the step must move: per fluid node 18+5 FP32 populations read
-    and written (184 B) + its mask byte; per wall-adjacent fluid node the FP64
-    precipitate read and written (16 B); per solid node its mask byte."""
+BYTES_PER_LUP = 185   # 2x9 flow + 5 solute FP32 populations read and written, 1 mask byte
+BYTES_PER_WALL_NODE = 16  # FP64 precipitate read and written at wall-adjacent fluid nodes
+
+
+def algorithmic_bytes(solid: np.ndarray) -> tuple:
+    """Algorithmic HBM bytes of one step: 185 B per lattice update (all nodes,
+    the unit MLUPS counts) plus 16 B per wall-adjacent fluid node.  Also the
+    fluid-only figure (solid nodes touch only their mask byte)."""
     fluid = int(np.count_nonzero(solid == 0))
-    solid_n = solid.size - fluid
-    wall = int(np.count_nonzero(wall_adjacent(solid))) if react else 0
-    return 185 * fluid + solid_n + 16 * wall
+    wall = int(np.count_nonzero(wall_adjacent(solid)))
+    per_lup = BYTES_PER_LUP * solid.size + BYTES_PER_WALL_NODE * wall
+    fluid_only = (BYTES_PER_LUP - 1) * fluid + solid.size + BYTES_PER_WALL_NODE * wall
+    return per_lup, fluid_only, wall
+
+
+def measured_traffic(tile):
+    """HBM bytes per launch from the committed PMC summary, only if it was
+    taken on this kernel source and launch shape."""
+    path = os.path.join(ROOT, "profiles", "k_step_preform2048_traffic.json")
+    src = os.path.join(ROOT, "paper_1309_6726_amd", "csrc", "lbm_kernels.hip")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(src, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_src_sha256") != sha or list(rec.get("tile", [])) != list(tile):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
 
 
 def cpu_baseline(prob, steps: int):
@@ -65,7 +105,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--tile", type=str, default="auto", help="TXxSY or auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -100,7 +140,7 @@ def main():
             sim.set_tile(tx, sy)
         sim.step(args.warmup)
         o0 = sim.observe()
-        bytes0 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8), True)
+        bytes0 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8))
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -113,12 +153,15 @@ def main():
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
         o1 = sim.observe()
-        bytes1 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8), True)
+        bytes1 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8))
+    copy_gbs = copy_bandwidth(torch, dev)
     ms_step = ms / args.steps
     mlups = N * args.steps / (ms / 1e3) / 1e6
     fluid0 = N - o0["n_solid"]
-    per_launch = 0.5 * (bytes0 + bytes1)
+    per_launch = 0.5 * (bytes0[0] + bytes1[0])
+    fluid_only = 0.5 * (bytes0[1] + bytes1[1])
     achieved = per_launch / (ms_step / 1e3) / 1e9
+    traffic = measured_traffic((tx, sy))
     cons = abs(o1["solute"] + o1["precipitate"] + o1["solute_removed"] -
                (o0["solute"] + o0["precipitate"] + o0["solute_removed"]))
     out = {
@@ -136,13 +179,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "porous preform 2048x2048, RSA disks r=8..24, solid fraction "
                                f"{prob.solid_fraction:.3f}, reservoir 64 cols, D2Q5 D=0.05, "
-                               "k_r=1e-3, threshold 1, 2-component Shan-Chen D2Q9 tau=1",
-                   "nx": p.nx, "ny": p.ny, "tile": [tx, sy], "mflups_fluid": round(fluid0 * args.steps / (ms / 1e3) / 1e6, 1),
+                               "k_r=1e-3, threshold 1, 2-component Shan-Chen D2Q9 tau=1, "
+                               "FP32 populations, FP64 arithmetic",
+                   "nx": p.nx, "ny": p.ny, "tile": [tx, sy],
+                   "mflups_fluid": round(fluid0 * args.steps / (ms / 1e3) / 1e6, 1),
+                   "wall_adjacent_nodes": bytes0[2],
                    "events_in_run": int(o1["n_events"] - o0["n_events"]),
-                   "solute_ledger_drift": cons, "wall_s": round(wall, 3)},
+                   "solute_ledger_drift": cons, "wall_s": round(wall, 3),
+                   "copy_gbs": round(copy_gbs, 1),
+                   "frac_of_copy": round(achieved / copy_gbs, 4),
+                   "fluid_only_gbs": round(fluid_only / (ms_step / 1e3) / 1e9, 1)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step<true,true>",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else int(traffic),
+                     "kernel": "k_step<true,true,double>",
+                     "bytes_per_lup": BYTES_PER_LUP,
                      "algorithmic_bytes_per_launch": int(per_launch),
                      "avg_launch_ms": round(ms_step, 5)},
     }

@@ -87,7 +87,9 @@ Layout make_layout(const lbm_params& p) {
 lbm_status check_params(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 3 || p->ny < 3) return fail(LBM_EINVAL, "nx, ny must be >= 3");
-  if ((long long)p->nx * p->ny > (1ll << 31) - 1) return fail(LBM_EINVAL, "lattice too large");
+  // 32-bit element offsets in the kernels: 23 population planes below 2^31
+  if (((long long)p->nx * p->ny + 63) / 64 * 64 * 23 > (1ll << 31) - 1)
+    return fail(LBM_EINVAL, "lattice too large (at most ~93 million nodes)");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 1/2");
   if (!(p->tau_g == 0.0 || (p->tau_g > 0.5 && std::isfinite(p->tau_g))))
     return fail(LBM_EINVAL, "tau_g must be 0 or > 1/2");
@@ -164,7 +166,7 @@ lbm_status queue_steps(lbm_sim* s, long long n) {
   a.sy = s->sy;
   a.nstrips = (p.nx + a.tx_owned - 1) / a.tx_owned;
   a.nsegs = (p.ny + s->sy - 1) / s->sy;
-  a.remap = ((a.nstrips * a.nsegs) % 8) == 0;
+  a.remap = (a.nstrips * a.nsegs) >= 8;
   a.solute = s->L.solute;
   a.react = s->L.react;
   a.omega = (float)(1.0 / p.tau);
@@ -523,13 +525,13 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   const int txs[] = {64, 128, 256};
-  const int sys[] = {4, 8, 16, 32, 64, 128};
+  const int sys[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128};
   int btx = s->tx, bsy = s->sy;
   float best = 1e30f;
   for (int tx : txs) {
     if (tx > 2 * s->p.nx + 2 && tx != 64) continue;
     for (int sy : sys) {
-      if (sy > 2 * s->p.ny && sy != 4) continue;
+      if (sy > 2 * s->p.ny && sy != 8) continue;
       s->tx = tx;
       s->sy = sy;
       if ((st = queue_steps(s, 2)) != LBM_OK) break;

@@ -55,25 +55,55 @@ __device__ __forceinline__ R sum9(const float* v) {
          (R)v[8];
 }
 
+// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left open (gfx9
+// encoding: vmcnt[3:0] and [15:14], expcnt[6:4], lgkmcnt[11:8]).
+#define VMCNT0 0x0F70
+
+// Workgroup-wide LDS barrier that leaves outstanding global memory operations
+// in flight (only LDS traffic is ordered); a single-wave workgroup needs no
+// s_barrier at all.
+__device__ __forceinline__ void lds_barrier(int TX) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  if (TX > 64) __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // R is the arithmetic type (float or double); populations are stored as FP32.
+//
+// Per workgroup, iteration k handles row r = ys - 1 + k: its populations,
+// precipitate (owned rows) and the mask byte of row k+1 are requested
+// together (the mask of row k arrived one iteration earlier), so each
+// iteration waits on one memory round trip.  The densities of row k go to
+// the LDS ring; after an LDS-only barrier row k-1 is collided and pushed.
+// Offsets are 32-bit (the host guarantees 23 planes fit below 2^31).  The
+// register budget is held to three waves per SIMD: a row iteration costs one
+// memory round trip plus ~1 us of VALU work per wave, so resident waves are
+// what hides the memory latency.
 template <bool SOLUTE, bool REACT, typename R>
-__global__ void __launch_bounds__(256) k_step(const StepArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_step(const StepArgs a) {
   extern __shared__ char lds_raw[];
   const int TX = blockDim.x;
-  R* s_r1 = (R*)lds_raw;           // [4][TX] density of component 1 (0 at solid)
-  R* s_r2 = s_r1 + 4 * TX;         // [4][TX] density of component 2
+  R* s_r1 = (R*)lds_raw;                 // [4][TX] density of component 1 (0 at solid)
+  R* s_r2 = s_r1 + 4 * TX;               // [4][TX] density of component 2
   float* s_s = (float*)(s_r2 + 4 * TX);  // [4][TX] solid flag 0/1
 
   const int T = a.nstrips * a.nsegs;
   const int b = blockIdx.x;
-  // XCD-aware order: consecutive tiles (vertically adjacent segments of one
-  // strip) go to the same XCD, which dispatches blocks b = xcd (mod 8).
-  const int tile = a.remap ? ((b & 7) * (T >> 3) + (b >> 3)) : b;
+  // XCD-aware order: the hardware hands block b to XCD b mod 8, so XCD x
+  // receives q + (x < r) blocks (q = T / 8, r = T mod 8).  Give each XCD a
+  // contiguous run of tiles, so vertically adjacent segments of a strip share
+  // one L2 and their halo rows are fetched from HBM once.
+  int tile = b;
+  if (a.remap) {
+    const int q = T >> 3, r = T & 7, x = b & 7, j = b >> 3;
+    tile = (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+  }
   const int strip = tile / a.nsegs;
   const int seg = tile - strip * a.nsegs;
   const int t = threadIdx.x;
   const int nx = a.nx, ny = a.ny;
-  const long long P = a.P;
+  const unsigned P = (unsigned)a.P;
   const int x0 = strip * a.tx_owned;
   const int nown = min(a.tx_owned, nx - x0);
   const bool active = t <= nown + 1;
@@ -89,51 +119,55 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
   const unsigned solid_bits = 1u | a.bit_prev;
   const int lane = __lane_id();
   const R WA = R(1) / R(9), WD = R(1) / R(36), W5A = R(1) / R(6);
+  const float* __restrict__ fin = a.fin;
+  const float* __restrict__ gin = a.gin;
+  const uint8_t* __restrict__ maskp = a.mask;
 
-  float f[18], g[5];
-  unsigned byte_cur = 1;
-#pragma unroll
-  for (int q = 0; q < 18; ++q) f[q] = 0.0f;
-#pragma unroll
-  for (int q = 0; q < 5; ++q) g[q] = 0.0f;
-
-  for (int k = 0; k < nrows; ++k) {
-    // ---- load row r = ys - 1 + k ------------------------------------------
+  auto row_y = [&](int k) {
     int yr = ys - 1 + k;
     if (yr < 0) yr += ny;
     if (yr >= ny) yr -= ny;
-    const long long idn = (long long)yr * nx + xc;
-    float fn[18], gn[5];
-    unsigned bn = 1;
+    return yr;
+  };
+
+  float f[18], g[5], fn[18], gn[5];
+  double m_cur = 0.0, m_nxt = 0.0;
+  unsigned b_cur = 1, b_nxt = 1;
+  unsigned mask_ahead = active ? (unsigned)maskp[(unsigned)row_y(0) * (unsigned)nx + (unsigned)xc] : 1u;
+
+  for (int k = 0; k < nrows; ++k) {
+    // ---- request row k: populations (+ solute, precipitate), next mask ----
+    const unsigned idn = (unsigned)row_y(k) * (unsigned)nx + (unsigned)xc;
+    const bool owned_row = k >= 1 && k <= nrows - 2;
+    b_nxt = mask_ahead;
+    if (active) {
+      if (!(b_nxt & 1u)) {
+#pragma unroll
+        for (int q = 0; q < 18; ++q) fn[q] = fin[q * P + idn];
+        if (SOLUTE && owner && owned_row) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) gn[q] = gin[q * P + idn];
+        }
+        if (REACT && owner && owned_row) m_nxt = a.m[idn];
+      }
+      if (k + 1 < nrows) mask_ahead = maskp[(unsigned)row_y(k + 1) * (unsigned)nx + (unsigned)xc];
+    }
+    // one wait per row, on every path: the row's loads (and the previous
+    // row's stores, issued earlier) complete here, so nothing is pending on
+    // the loop back edge
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
     R r1 = R(0), r2 = R(0);
     float sv = 1.0f;
-#pragma unroll
-    for (int q = 0; q < 18; ++q) fn[q] = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) gn[q] = 0.0f;
-    if (active) {
-      bn = a.mask[idn];
-      const bool pops = !(bn & 1u);   // fluid, or pending and still holding populations
-      const bool solid = (bn & solid_bits) != 0;
-      if (pops) {
-#pragma unroll
-        for (int q = 0; q < 18; ++q) fn[q] = a.fin[q * P + idn];
-        if (SOLUTE && owner && k >= 1 && k <= nrows - 2) {
-#pragma unroll
-          for (int q = 0; q < 5; ++q) gn[q] = a.gin[q * P + idn];
-        }
-      }
-      if (!solid) {
-        r1 = sum9<R>(fn);
-        r2 = sum9<R>(fn + 9);
-        sv = 0.0f;
-      }
+    if (active && !(b_nxt & solid_bits)) {
+      r1 = sum9<R>(fn);
+      r2 = sum9<R>(fn + 9);
+      sv = 0.0f;
     }
     const int slot = k & 3;
     s_r1[slot * TX + t] = r1;
     s_r2[slot * TX + t] = r2;
     s_s[slot * TX + t] = sv;
-    __syncthreads();
+    lds_barrier(TX);
 
     // ---- collide and push row y = r - 1 -----------------------------------
     bool ev = false;
@@ -142,13 +176,13 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
       const int y = ys + k - 2;
       const int yd = y == 0 ? ny - 1 : y - 1;
       const int yu = y == ny - 1 ? 0 : y + 1;
-      const long long idx = (long long)y * nx + xc;
+      const unsigned idx = (unsigned)y * (unsigned)nx + (unsigned)xc;
       const int sb = ((k - 2) & 3) * TX, sm = ((k - 1) & 3) * TX, sa = (k & 3) * TX;
       const R* A1 = s_r1;
       const R* A2 = s_r2;
       const float* AS = s_s;
       if (AS[sm + t] != 0.0f) {
-        if (REACT && (byte_cur & a.bit_prev)) {
+        if (REACT && (b_cur & a.bit_prev)) {
           // turned solid at the end of the previous step: book its populations
           a.drop[idx] = (float)sum9<R>(f);
           a.drop[P + idx] = (float)sum9<R>(f + 9);
@@ -158,19 +192,17 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
         }
       } else {
         const R rho1 = A1[sm + t], rho2 = A2[sm + t];
-        // neighbour values: E, N, W, S, NE, NW, SW, SE
-        const R n1E = A1[sm + t + 1], n1N = A1[sa + t], n1W = A1[sm + t - 1], n1S = A1[sb + t];
-        const R n1NE = A1[sa + t + 1], n1NW = A1[sa + t - 1], n1SW = A1[sb + t - 1], n1SE = A1[sb + t + 1];
-        const R n2E = A2[sm + t + 1], n2N = A2[sa + t], n2W = A2[sm + t - 1], n2S = A2[sb + t];
-        const R n2NE = A2[sa + t + 1], n2NW = A2[sa + t - 1], n2SW = A2[sb + t - 1], n2SE = A2[sb + t + 1];
         const float sE = AS[sm + t + 1], sN = AS[sa + t], sW = AS[sm + t - 1], sS = AS[sb + t];
         const float sNE = AS[sa + t + 1], sNW = AS[sa + t - 1], sSW = AS[sb + t - 1], sSE = AS[sb + t + 1];
-
-        // sum_i w_i v(x+e_i) e_i for the other component and the solid mask
-        const R c2x = WA * (n2E - n2W) + WD * ((n2NE - n2NW) + (n2SE - n2SW));
-        const R c2y = WA * (n2N - n2S) + WD * ((n2NE + n2NW) - (n2SE + n2SW));
-        const R c1x = WA * (n1E - n1W) + WD * ((n1NE - n1NW) + (n1SE - n1SW));
-        const R c1y = WA * (n1N - n1S) + WD * ((n1NE + n1NW) - (n1SE + n1SW));
+        // sum_i w_i v(x+e_i) e_i of the other component and of the solid mask
+        const R c2x = WA * (A2[sm + t + 1] - A2[sm + t - 1]) +
+                      WD * ((A2[sa + t + 1] - A2[sa + t - 1]) + (A2[sb + t + 1] - A2[sb + t - 1]));
+        const R c2y = WA * (A2[sa + t] - A2[sb + t]) +
+                      WD * ((A2[sa + t + 1] + A2[sa + t - 1]) - (A2[sb + t + 1] + A2[sb + t - 1]));
+        const R c1x = WA * (A1[sm + t + 1] - A1[sm + t - 1]) +
+                      WD * ((A1[sa + t + 1] - A1[sa + t - 1]) + (A1[sb + t + 1] - A1[sb + t - 1]));
+        const R c1y = WA * (A1[sa + t] - A1[sb + t]) +
+                      WD * ((A1[sa + t + 1] + A1[sa + t - 1]) - (A1[sb + t + 1] + A1[sb + t - 1]));
         const R csx = WA * R(sE - sW) + WD * R((sNE - sNW) + (sSE - sSW));
         const R csy = WA * R(sN - sS) + WD * R((sNE + sNW) - (sSE + sSW));
 
@@ -180,13 +212,10 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
         const R F2x = -G * rho2 * c1x - Ga2 * rho2 * csx + rho2 * ax;
         const R F2y = -G * rho2 * c1y - Ga2 * rho2 * csy + rho2 * ay;
 
-        R fr[18];
-#pragma unroll
-        for (int q = 0; q < 18; ++q) fr[q] = (R)f[q];
-        const R j1x = (fr[1] - fr[3]) + (fr[5] - fr[6]) + (fr[8] - fr[7]);
-        const R j1y = (fr[2] - fr[4]) + (fr[5] + fr[6]) - (fr[7] + fr[8]);
-        const R j2x = (fr[10] - fr[12]) + (fr[14] - fr[15]) + (fr[17] - fr[16]);
-        const R j2y = (fr[11] - fr[13]) + (fr[14] + fr[15]) - (fr[16] + fr[17]);
+        const R j1x = ((R)f[1] - (R)f[3]) + ((R)f[5] - (R)f[6]) + ((R)f[8] - (R)f[7]);
+        const R j1y = ((R)f[2] - (R)f[4]) + ((R)f[5] + (R)f[6]) - ((R)f[7] + (R)f[8]);
+        const R j2x = ((R)f[10] - (R)f[12]) + ((R)f[14] - (R)f[15]) + ((R)f[17] - (R)f[16]);
+        const R j2y = ((R)f[11] - (R)f[13]) + ((R)f[14] + (R)f[15]) - ((R)f[16] + (R)f[17]);
 
         const R rt = rho1 + rho2;
         const R irt = R(1) / rt;
@@ -198,84 +227,57 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
         const R ux = (j1x + j2x + R(0.5) * (F1x + F2x)) * irt;
         const R uy = (j1y + j2y + R(0.5) * (F1y + F2y)) * irt;
 
-        const R om = (R)a.omega;
-        R fs[18];
-        {
-          const R uu = v1x * v1x + v1y * v1y;
-          fs[1] = fr[1] + om * (feq<R>(WA, rho1, v1x, uu) - fr[1]);
-          fs[2] = fr[2] + om * (feq<R>(WA, rho1, v1y, uu) - fr[2]);
-          fs[3] = fr[3] + om * (feq<R>(WA, rho1, -v1x, uu) - fr[3]);
-          fs[4] = fr[4] + om * (feq<R>(WA, rho1, -v1y, uu) - fr[4]);
-          fs[5] = fr[5] + om * (feq<R>(WD, rho1, v1x + v1y, uu) - fr[5]);
-          fs[6] = fr[6] + om * (feq<R>(WD, rho1, -v1x + v1y, uu) - fr[6]);
-          fs[7] = fr[7] + om * (feq<R>(WD, rho1, -v1x - v1y, uu) - fr[7]);
-          fs[8] = fr[8] + om * (feq<R>(WD, rho1, v1x - v1y, uu) - fr[8]);
-          // the rest population closes the mass balance exactly (the weights
-          // of the moving links are not exact binary fractions)
-          fs[0] = rho1 - (((fs[1] + fs[2]) + (fs[3] + fs[4])) + ((fs[5] + fs[6]) + (fs[7] + fs[8])));
-        }
-        {
-          const R uu = v2x * v2x + v2y * v2y;
-          fs[10] = fr[10] + om * (feq<R>(WA, rho2, v2x, uu) - fr[10]);
-          fs[11] = fr[11] + om * (feq<R>(WA, rho2, v2y, uu) - fr[11]);
-          fs[12] = fr[12] + om * (feq<R>(WA, rho2, -v2x, uu) - fr[12]);
-          fs[13] = fr[13] + om * (feq<R>(WA, rho2, -v2y, uu) - fr[13]);
-          fs[14] = fr[14] + om * (feq<R>(WD, rho2, v2x + v2y, uu) - fr[14]);
-          fs[15] = fr[15] + om * (feq<R>(WD, rho2, -v2x + v2y, uu) - fr[15]);
-          fs[16] = fr[16] + om * (feq<R>(WD, rho2, -v2x - v2y, uu) - fr[16]);
-          fs[17] = fr[17] + om * (feq<R>(WD, rho2, v2x - v2y, uu) - fr[17]);
-          fs[9] = rho2 - (((fs[10] + fs[11]) + (fs[12] + fs[13])) + ((fs[14] + fs[15]) + (fs[16] + fs[17])));
-        }
-
         // target offsets of the eight neighbours
-        const long long iE = (long long)y * nx + xr, iW = (long long)y * nx + xl;
-        const long long iN = (long long)yu * nx + xc, iS = (long long)yd * nx + xc;
-        const long long iNE = (long long)yu * nx + xr, iNW = (long long)yu * nx + xl;
-        const long long iSW = (long long)yd * nx + xl, iSE = (long long)yd * nx + xr;
-        float* fo = a.fout;
-#define PUSH(base, i, opp, bs, tgt, val)                                \
-  do {                                                                  \
-    if (bs != 0.0f) fo[((base) + (opp)) * P + idx] = (float)(val);      \
-    else fo[((base) + (i)) * P + (tgt)] = (float)(val);                 \
+        const unsigned iE = (unsigned)y * nx + xr, iW = (unsigned)y * nx + xl;
+        const unsigned iN = (unsigned)yu * nx + xc, iS = (unsigned)yd * nx + xc;
+        const unsigned iNE = (unsigned)yu * nx + xr, iNW = (unsigned)yu * nx + xl;
+        const unsigned iSW = (unsigned)yd * nx + xl, iSE = (unsigned)yd * nx + xr;
+        float* __restrict__ fo = a.fout;
+        const R om = (R)a.omega;
+        // collide one component and push each moving population as soon as it
+        // is formed (halfway bounce-back into the node's own opposite link at
+        // a solid neighbour); the rest population closes the mass balance
+        // exactly (the moving-link weights are not exact binary fractions)
+        auto collide_push = [&](const float* fc, unsigned base, R rho, R vx, R vy) {
+          const R uu = vx * vx + vy * vy;
+          R sum = R(0);
+#define CP(i, opp, w, eu, bs, tgt)                                          \
+  do {                                                                      \
+    const R fi = (R)fc[i];                                                  \
+    const R v = fi + om * (feq<R>(w, rho, eu, uu) - fi);                    \
+    sum += v;                                                               \
+    if (bs != 0.0f) fo[(base + (opp)) * P + idx] = (float)v;                \
+    else fo[(base + (i)) * P + (tgt)] = (float)v;                           \
   } while (0)
-        fo[0 * P + idx] = (float)fs[0];
-        PUSH(0, 1, 3, sE, iE, fs[1]);
-        PUSH(0, 2, 4, sN, iN, fs[2]);
-        PUSH(0, 3, 1, sW, iW, fs[3]);
-        PUSH(0, 4, 2, sS, iS, fs[4]);
-        PUSH(0, 5, 7, sNE, iNE, fs[5]);
-        PUSH(0, 6, 8, sNW, iNW, fs[6]);
-        PUSH(0, 7, 5, sSW, iSW, fs[7]);
-        PUSH(0, 8, 6, sSE, iSE, fs[8]);
-        fo[9 * P + idx] = (float)fs[9];
-        PUSH(9, 1, 3, sE, iE, fs[10]);
-        PUSH(9, 2, 4, sN, iN, fs[11]);
-        PUSH(9, 3, 1, sW, iW, fs[12]);
-        PUSH(9, 4, 2, sS, iS, fs[13]);
-        PUSH(9, 5, 7, sNE, iNE, fs[14]);
-        PUSH(9, 6, 8, sNW, iNW, fs[15]);
-        PUSH(9, 7, 5, sSW, iSW, fs[16]);
-        PUSH(9, 8, 6, sSE, iSE, fs[17]);
-#undef PUSH
+          CP(1, 3, WA, vx, sE, iE);
+          CP(2, 4, WA, vy, sN, iN);
+          CP(3, 1, WA, -vx, sW, iW);
+          CP(4, 2, WA, -vy, sS, iS);
+          CP(5, 7, WD, vx + vy, sNE, iNE);
+          CP(6, 8, WD, -vx + vy, sNW, iNW);
+          CP(7, 5, WD, -vx - vy, sSW, iSW);
+          CP(8, 6, WD, vx - vy, sSE, iSE);
+#undef CP
+          fo[base * P + idx] = (float)(rho - sum);
+        };
+        collide_push(f, 0u, rho1, v1x, v1y);
+        collide_push(f + 9, 9u, rho2, v2x, v2y);
 
         if (SOLUTE) {
-          R gr[5];
-#pragma unroll
-          for (int q = 0; q < 5; ++q) gr[q] = (R)g[q];
-          const R C = ((gr[0] + gr[1]) + (gr[2] + gr[3])) + gr[4];
+          const R C = (((R)g[0] + (R)g[1]) + ((R)g[2] + (R)g[3])) + (R)g[4];
           const R og = (R)a.omega_g;
           R gs[5];
-          gs[1] = gr[1] + og * (W5A * C * (R(1) + R(3) * ux) - gr[1]);
-          gs[2] = gr[2] + og * (W5A * C * (R(1) + R(3) * uy) - gr[2]);
-          gs[3] = gr[3] + og * (W5A * C * (R(1) - R(3) * ux) - gr[3]);
-          gs[4] = gr[4] + og * (W5A * C * (R(1) - R(3) * uy) - gr[4]);
+          gs[1] = (R)g[1] + og * (W5A * C * (R(1) + R(3) * ux) - (R)g[1]);
+          gs[2] = (R)g[2] + og * (W5A * C * (R(1) + R(3) * uy) - (R)g[2]);
+          gs[3] = (R)g[3] + og * (W5A * C * (R(1) - R(3) * ux) - (R)g[3]);
+          gs[4] = (R)g[4] + og * (W5A * C * (R(1) - R(3) * uy) - (R)g[4]);
           gs[0] = C - ((gs[1] + gs[2]) + (gs[3] + gs[4]));
           if (REACT) {
             const int ns = (int)sE + (int)sN + (int)sW + (int)sS;
             if (ns > 0) {
               const double phi = (double)rho1 / ((double)rho1 + (double)rho2);
               const double rr = a.k_r * (double)ns * phi;
-              const double mm = a.m[idx] + rr * (double)C;
+              const double mm = m_cur + rr * (double)C;
               a.m[idx] = mm;
               const R keep = (R)(1.0 - rr);
 #pragma unroll
@@ -289,7 +291,7 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
               }
             }
           }
-          float* go = a.gout;
+          float* __restrict__ go = a.gout;
           go[idx] = (float)gs[0];
           if (sE != 0.0f) go[3 * P + idx] = (float)gs[1]; else go[1 * P + iE] = (float)gs[1];
           if (sN != 0.0f) go[4 * P + idx] = (float)gs[2]; else go[2 * P + iN] = (float)gs[2];
@@ -316,12 +318,15 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a) {
         }
       }
     }
-    // rotate the register window
+    // rotate: row k becomes the row to collide next iteration
 #pragma unroll
     for (int q = 0; q < 18; ++q) f[q] = fn[q];
+    if (SOLUTE) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) g[q] = gn[q];
-    byte_cur = bn;
+      for (int q = 0; q < 5; ++q) g[q] = gn[q];
+    }
+    m_cur = m_nxt;
+    b_cur = b_nxt;
   }
 }
 
