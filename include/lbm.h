@@ -170,6 +170,60 @@ lbm_status lbm_set_arith(lbm_sim* sim, int32_t bits);
 lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_candidate, int32_t* tx, int32_t* sy,
                         double* best_ms_per_step);
 
+/* ------------------------------------------------------------------------
+ * Batched sweeps: many independent lattices of different sizes and
+ * parameters advanced together, one launch per step for the whole batch (a
+ * flat list of (instance, strip, segment) tiles), optionally replayed from a
+ * captured HIP graph of `chunk` steps.  Every instance computes exactly what
+ * lbm_step computes for it alone (bit for bit).  All instances share tau, G,
+ * accel and the solute/reaction switches; the rest of lbm_params is per
+ * instance.  Front positions can be recorded into a device table at chosen
+ * steps without synchronising (used to sample z(t) for parameter sweeps).
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* Device memory for n instances (p: n records) and an n x nslots front table. */
+lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, int32_t nslots, size_t* bytes);
+
+/* As lbm_init for each instance i (solid[i], rho1[i], rho2[i], conc[i] host
+ * arrays of its own size; conc may be NULL when tau_g == 0).  The inputs stay
+ * staged in the workspace so the batch can be reset to its initial state. */
+lbm_status lbm_batch_init(int32_t n, const lbm_params* p, const uint8_t* const* solid,
+                          const double* const* rho1, const double* const* rho2,
+                          const double* const* conc, int32_t nslots, void* stream,
+                          void* workspace, size_t ws_bytes, lbm_batch** out);
+
+/* Launch shape (tx 64/128/256, sy >= 8); changes no result bit. */
+lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t tx, int32_t sy);
+lbm_status lbm_batch_get_tile(const lbm_batch* b, int32_t* tx, int32_t* sy);
+
+/* chunk > 0: lbm_batch_step replays a HIP graph of `chunk` captured steps
+ * (captured at first use) and launches the remainder directly; 0: direct. */
+lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t chunk);
+
+/* Queue nsteps steps of every instance (asynchronous). */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps);
+
+/* Queue: front position of every instance into column `slot` of the table
+ * (NaN for instances with W == 0).  lbm_batch_fronts copies the n x nslots
+ * table (row-major) to the host and synchronises. */
+lbm_status lbm_batch_record_fronts(lbm_batch* b, int32_t slot);
+lbm_status lbm_batch_fronts(lbm_batch* b, double* host);
+
+/* Per-instance observables, fields and growth events (as the single-lattice
+ * calls; synchronise). */
+lbm_status lbm_batch_observe(lbm_batch* b, int32_t i, lbm_obs* out);
+lbm_status lbm_batch_fields(lbm_batch* b, int32_t i, uint32_t field_mask, double* host_fields);
+lbm_status lbm_batch_events(lbm_batch* b, int32_t i, int64_t first, lbm_event* buf, int64_t cap,
+                            int64_t* n);
+
+/* Before the first step only: time the launch shapes, keep the fastest and
+ * reset every instance to its initial state. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* tx, int32_t* sy,
+                              double* best_ms_per_step);
+
+void lbm_batch_destroy(lbm_batch* b);
+
 void lbm_destroy(lbm_sim* sim);
 const char* lbm_strerror(lbm_status s);
 const char* lbm_last_error(void);

@@ -562,3 +562,516 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
 void lbm_destroy(lbm_sim* s) { free(s); }
 
 }  // extern "C"
+
+// ===========================================================================
+// Batched sweep: many independent lattices advanced by one launch per step.
+// ===========================================================================
+
+struct lbm_batch {
+  int n;
+  std::vector<lbm_params> p;
+  std::vector<Layout> L;
+  std::vector<size_t> base;   // workspace offset of each instance's buffers
+  std::vector<size_t> stage;  // workspace offset of each instance's FP64 inputs
+  hipStream_t stream;
+  char* ws;
+  StepArgs* d_insts;          // [n][2]: arguments for state parity 0 and 1
+  std::vector<StepArgs> h_insts;
+  int4* d_tiles;
+  int max_tiles, ntiles;
+  int4* d_capi;
+  long long* d_step;
+  double* d_table;
+  int nslots;
+  double* d_partial;
+  double* d_out;
+  int max_blocks;
+  long long step;
+  int tx, sy, arith64;
+  bool solute, react, poisoned;
+  int graph_chunk;
+  hipGraphExec_t graph;
+  hipStream_t cap_stream;     // library-owned stream used only to capture the graph
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t insts, tiles, capi, stepc, table, partial, out, common, total;
+  std::vector<Layout> L;
+  std::vector<size_t> base, stage;
+  int max_tiles, max_blocks;
+};
+
+int tiles_for(const lbm_params& p, int tx, int sy) {
+  return ((p.nx + tx - 3) / (tx - 2)) * ((p.ny + sy - 1) / sy);
+}
+
+lbm_status batch_layout(int n, const lbm_params* p, int nslots, BatchLayout* B) {
+  if (n < 1 || !p) return fail(LBM_EINVAL, "batch needs n >= 1 parameter records");
+  if (nslots < 0 || nslots > 4096) return fail(LBM_EINVAL, "nslots must be in [0, 4096]");
+  const bool solute = p[0].tau_g > 0.0, react = p[0].k_r > 0.0;
+  B->max_tiles = 0;
+  B->max_blocks = 1;
+  for (int i = 0; i < n; ++i) {
+    lbm_status st = check_params(&p[i]);
+    if (st != LBM_OK) return fail(st, "instance %d: %s", i, g_err.c_str());
+    if (p[i].tau != p[0].tau || p[i].G != p[0].G || p[i].accel[0] != p[0].accel[0] ||
+        p[i].accel[1] != p[0].accel[1])
+      return fail(LBM_EINVAL, "instance %d: tau, G and accel must be shared by the batch", i);
+    if ((p[i].tau_g > 0.0) != solute || (p[i].k_r > 0.0) != react)
+      return fail(LBM_EINVAL, "instance %d: solute/reaction switches must be shared", i);
+    B->max_tiles += tiles_for(p[i], 64, 8);
+    B->max_blocks = std::max(B->max_blocks, (int)std::min<long long>(1024, ((long long)p[i].nx * p[i].ny + 255) / 256));
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = a256(off + bytes);
+    return o;
+  };
+  B->insts = take((size_t)2 * n * sizeof(StepArgs));
+  B->tiles = take((size_t)B->max_tiles * sizeof(int4));
+  B->capi = take((size_t)n * sizeof(int4));
+  B->stepc = take(sizeof(long long));
+  B->table = take((size_t)n * std::max(nslots, 1) * sizeof(double));
+  B->partial = take((size_t)B->max_blocks * OBS_SLOTS * sizeof(double));
+  B->out = take(OBS_OUT * sizeof(double));
+  B->common = off;
+  B->L.clear();
+  B->base.clear();
+  B->stage.clear();
+  for (int i = 0; i < n; ++i) {
+    Layout li = make_layout(p[i]);
+    B->L.push_back(li);
+    B->base.push_back(take(li.total));
+    B->stage.push_back(take((size_t)3 * li.N * sizeof(double) + li.N));
+  }
+  B->total = off;
+  return LBM_OK;
+}
+
+StepArgs instance_args(const lbm_batch* b, int i, int parity) {
+  const lbm_params& p = b->p[i];
+  const Layout& L = b->L[i];
+  char* w = b->ws + b->base[i];
+  StepArgs a{};
+  a.fin = (float*)(w + L.f[parity]);
+  a.fout = (float*)(w + L.f[parity ^ 1]);
+  a.gin = L.solute ? (float*)(w + L.g[parity]) : nullptr;
+  a.gout = L.solute ? (float*)(w + L.g[parity ^ 1]) : nullptr;
+  a.mask = (uint8_t*)(w + L.mask);
+  a.m = L.react ? (double*)(w + L.m) : nullptr;
+  a.sstep = L.react ? (int32_t*)(w + L.sstep) : nullptr;
+  a.drop = L.react ? (float*)(w + L.drop) : nullptr;
+  a.ev = L.react ? (lbm_event*)(w + L.ev) : nullptr;
+  a.ev_count = (unsigned long long*)(w + L.evc);
+  a.ev_cap = L.ev_cap;
+  a.P = L.P;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.tx_owned = b->tx - 2;
+  a.sy = b->sy;
+  a.nstrips = (p.nx + a.tx_owned - 1) / a.tx_owned;
+  a.nsegs = (p.ny + b->sy - 1) / b->sy;
+  a.remap = 0;
+  a.solute = L.solute;
+  a.react = L.react;
+  a.omega = (float)(1.0 / p.tau);
+  a.tau = (float)p.tau;
+  a.G = (float)p.G;
+  a.Gads1 = (float)p.G_ads[0];
+  a.Gads2 = (float)p.G_ads[1];
+  a.ax = (float)p.accel[0];
+  a.ay = (float)p.accel[1];
+  a.omega_g = L.solute ? (float)(1.0 / p.tau_g) : 0.0f;
+  a.k_r = p.k_r;
+  a.threshold = p.threshold;
+  return a;
+}
+
+void drop_graph(lbm_batch* b) {
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+}
+
+// Rebuild the per-instance arguments and the tile list for the launch shape.
+lbm_status batch_configure(lbm_batch* b) {
+  drop_graph(b);
+  b->h_insts.resize(2 * b->n);
+  for (int i = 0; i < b->n; ++i) {
+    b->h_insts[2 * i] = instance_args(b, i, 0);
+    b->h_insts[2 * i + 1] = instance_args(b, i, 1);
+  }
+  std::vector<int4> order;
+  for (int i = 0; i < b->n; ++i) {
+    const int ns = (b->p[i].nx + b->tx - 3) / (b->tx - 2), nq = (b->p[i].ny + b->sy - 1) / b->sy;
+    for (int s = 0; s < ns; ++s)
+      for (int q = 0; q < nq; ++q) order.push_back(make_int4(i, s, q, 0));
+  }
+  const int T = (int)order.size();
+  if (T > b->max_tiles) return fail(LBM_EINVAL, "tile list exceeds its buffer");
+  std::vector<int4> tiles(T);
+  for (int k = 0; k < T; ++k) tiles[k] = T >= 8 ? order[host_xcd_tile(k, T)] : order[k];
+  b->ntiles = T;
+  HIPCHECK(hipMemcpyAsync(b->d_insts, b->h_insts.data(), b->h_insts.size() * sizeof(StepArgs),
+                          hipMemcpyHostToDevice, b->stream));
+  HIPCHECK(hipMemcpyAsync(b->d_tiles, tiles.data(), T * sizeof(int4), hipMemcpyHostToDevice, b->stream));
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+// Initial state of every instance from its staged FP64 inputs.
+lbm_status batch_reset(lbm_batch* b) {
+  drop_graph(b);
+  for (int i = 0; i < b->n; ++i) {
+    const Layout& L = b->L[i];
+    char* w = b->ws + b->base[i];
+    const double* st = (const double*)(b->ws + b->stage[i]);
+    // the mask is restored too: growth changes it
+    HIPCHECK(hipMemcpyAsync(w + L.mask, st + 3 * L.N, L.N, hipMemcpyDeviceToDevice, b->stream));
+    HIPCHECK(hipMemsetAsync(w + L.evc, 0, sizeof(unsigned long long), b->stream));
+    HIPCHECK(launch_init(st, st + L.N, L.solute ? st + 2 * L.N : nullptr,
+                         (const uint8_t*)(w + L.mask), (float*)(w + L.f[0]),
+                         L.solute ? (float*)(w + L.g[0]) : nullptr,
+                         L.react ? (double*)(w + L.m) : nullptr,
+                         L.react ? (int32_t*)(w + L.sstep) : nullptr,
+                         L.react ? (float*)(w + L.drop) : nullptr, L.N, L.P, L.solute, L.react,
+                         b->stream));
+  }
+  HIPCHECK(hipMemsetAsync(b->d_step, 0, sizeof(long long), b->stream));
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  b->step = 0;
+  return LBM_OK;
+}
+
+lbm_status batch_launch(lbm_batch* b, long long nsteps) {
+  for (long long t = 0; t < nsteps; ++t) {
+    hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, b->tx,
+                                     b->solute, b->react, b->arith64, b->stream);
+    if (e != hipSuccess) {
+      b->poisoned = true;
+      return fail(LBM_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
+    }
+  }
+  b->step += nsteps;
+  return LBM_OK;
+}
+
+lbm_status bguard(const lbm_batch* b) {
+  if (!b) return fail(LBM_EINVAL, "batch handle is NULL");
+  if (b->poisoned) return fail(LBM_ESTATE, "batch poisoned by an earlier failure");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_workspace_bytes(int32_t n, const lbm_params* p, int32_t nslots, size_t* bytes) {
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  BatchLayout B;
+  lbm_status st = batch_layout(n, p, nslots, &B);
+  if (st != LBM_OK) return st;
+  *bytes = B.total;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_init(int32_t n, const lbm_params* p, const uint8_t* const* solid,
+                          const double* const* rho1, const double* const* rho2,
+                          const double* const* conc, int32_t nslots, void* stream,
+                          void* workspace, size_t ws_bytes, lbm_batch** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  BatchLayout B;
+  lbm_status st = batch_layout(n, p, nslots, &B);
+  if (st != LBM_OK) return st;
+  if (!solid || !rho1 || !rho2) return fail(LBM_EINVAL, "solid, rho1, rho2 arrays are required");
+  if (!workspace || ((uintptr_t)workspace & 255u)) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < B.total) return fail(LBM_EINVAL, "workspace too small: %zu < %zu", ws_bytes, B.total);
+  const bool solute = p[0].tau_g > 0.0;
+  if (solute && !conc) return fail(LBM_EINVAL, "conc arrays are required when tau_g > 0");
+  for (int i = 0; i < n; ++i) {
+    const long long N = (long long)p[i].nx * p[i].ny;
+    if (!solid[i] || !rho1[i] || !rho2[i] || (solute && !conc[i]))
+      return fail(LBM_EINVAL, "instance %d: NULL input array", i);
+    for (long long k = 0; k < N; ++k) {
+      if (solid[i][k] > 1) return fail(LBM_EINVAL, "instance %d: mask value at node %lld", i, k);
+      if (solid[i][k]) continue;
+      if (!(rho1[i][k] >= 0.0) || !(rho2[i][k] >= 0.0) || !std::isfinite(rho1[i][k]) ||
+          !std::isfinite(rho2[i][k]) || rho1[i][k] + rho2[i][k] <= 0.0)
+        return fail(LBM_EINVAL, "instance %d: bad density at node %lld", i, k);
+      if (solute && (!(conc[i][k] >= 0.0) || !std::isfinite(conc[i][k])))
+        return fail(LBM_EINVAL, "instance %d: bad concentration at node %lld", i, k);
+    }
+  }
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return fail(LBM_ENOMEM, "batch handle");
+  b->n = n;
+  b->p.assign(p, p + n);
+  b->L = B.L;
+  b->base = B.base;
+  b->stage = B.stage;
+  b->stream = (hipStream_t)stream;
+  b->ws = (char*)workspace;
+  b->d_insts = (StepArgs*)(b->ws + B.insts);
+  b->d_tiles = (int4*)(b->ws + B.tiles);
+  b->max_tiles = B.max_tiles;
+  b->d_capi = (int4*)(b->ws + B.capi);
+  b->d_step = (long long*)(b->ws + B.stepc);
+  b->d_table = (double*)(b->ws + B.table);
+  b->nslots = nslots;
+  b->d_partial = (double*)(b->ws + B.partial);
+  b->d_out = (double*)(b->ws + B.out);
+  b->max_blocks = B.max_blocks;
+  b->tx = 128;
+  b->sy = 24;
+  b->arith64 = 1;
+  b->solute = solute;
+  b->react = p[0].k_r > 0.0;
+  b->graph = nullptr;
+  b->graph_chunk = 0;
+  b->cap_stream = nullptr;
+  std::vector<int4> capi(n);
+  for (int i = 0; i < n; ++i) {
+    const long long N = b->L[i].N;
+    char* stg = b->ws + b->stage[i];
+    char* w = b->ws + b->base[i];
+    capi[i] = make_int4(p[i].x_in, p[i].x_out, p[i].y0, p[i].W);
+#define BCK(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) { delete b; return fail(LBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); } } while (0)
+    BCK(hipMemcpyAsync(stg, rho1[i], N * 8, hipMemcpyHostToDevice, b->stream));
+    BCK(hipMemcpyAsync(stg + N * 8, rho2[i], N * 8, hipMemcpyHostToDevice, b->stream));
+    if (solute) BCK(hipMemcpyAsync(stg + 2 * N * 8, conc[i], N * 8, hipMemcpyHostToDevice, b->stream));
+    BCK(hipMemcpyAsync(stg + 3 * N * 8, solid[i], N, hipMemcpyHostToDevice, b->stream));
+  }
+  BCK(hipMemcpyAsync(b->d_capi, capi.data(), n * sizeof(int4), hipMemcpyHostToDevice, b->stream));
+#undef BCK
+  if ((st = batch_configure(b)) != LBM_OK || (st = batch_reset(b)) != LBM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t tx, int32_t sy) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (!(tx == 64 || tx == 128 || tx == 256) || sy < 8 || sy > 4096)
+    return fail(LBM_EINVAL, "batch tile %d x %d not supported (tx 64/128/256, sy >= 8)", tx, sy);
+  b->tx = tx;
+  b->sy = sy;
+  return batch_configure(b);
+}
+
+lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t chunk) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (chunk < 0 || chunk > 100000) return fail(LBM_EINVAL, "chunk must be in [0, 100000]");
+  drop_graph(b);
+  b->graph_chunk = chunk;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  long long left = nsteps;
+  if (b->graph_chunk > 0 && left >= b->graph_chunk) {
+    if (!b->graph) {
+      // capture chunk steps once; the kernels read the step index from the
+      // device counter, so every replay continues where the last one ended
+      // captured on a library-owned stream (the caller's may be the legacy
+      // default stream, which cannot be captured), launched on the caller's
+      hipGraph_t g = nullptr;
+      if (!b->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+      HIPCHECK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      for (int t = 0; t < b->graph_chunk; ++t) {
+        hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, b->tx,
+                                         b->solute, b->react, b->arith64, b->cap_stream);
+        if (e != hipSuccess) {
+          (void)hipStreamEndCapture(b->cap_stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          return fail(LBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        }
+      }
+      HIPCHECK(hipStreamEndCapture(b->cap_stream, &g));
+      hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->graph = nullptr;
+        return fail(LBM_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+      }
+    }
+    while (left >= b->graph_chunk) {
+      HIPCHECK(hipGraphLaunch(b->graph, b->stream));
+      left -= b->graph_chunk;
+      b->step += b->graph_chunk;
+    }
+  }
+  return batch_launch(b, left);
+}
+
+lbm_status lbm_batch_record_fronts(lbm_batch* b, int32_t slot) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (slot < 0 || slot >= b->nslots) return fail(LBM_EINVAL, "slot out of range");
+  HIPCHECK(launch_front_batch(b->d_insts, b->d_capi, b->d_step, b->n, slot, b->nslots, b->d_table,
+                              b->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_fronts(lbm_batch* b, double* host) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (!host) return fail(LBM_EINVAL, "host is NULL");
+  HIPCHECK(hipMemcpyAsync(host, b->d_table, (size_t)b->n * b->nslots * sizeof(double),
+                          hipMemcpyDeviceToHost, b->stream));
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_observe(lbm_batch* b, int32_t i, lbm_obs* o) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (i < 0 || i >= b->n || !o) return fail(LBM_EINVAL, "bad instance or NULL out");
+  const lbm_params& p = b->p[i];
+  const StepArgs& a = b->h_insts[2 * i + (int)(b->step & 1)];
+  const Layout& L = b->L[i];
+  const unsigned bp = pending_bit(b->step - 1);
+  const int nblocks = (int)std::min<long long>(b->max_blocks, (L.N + 255) / 256);
+  hipError_t e = launch_observe(a.fin, a.gin, a.mask, a.m, a.drop, a.sstep, L.N, L.P, p.nx, bp,
+                                L.solute, L.react, nblocks, b->d_partial, b->d_out, p.x_in, p.x_out,
+                                p.y0, p.W, b->stream);
+  double h[OBS_OUT];
+  unsigned long long nev = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(h, b->d_out, sizeof h, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nev, a.ev_count, sizeof nev, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) { b->poisoned = true; return fail(LBM_EDEVICE, "batch observe: %s", hipGetErrorString(e)); }
+  memset(o, 0, sizeof *o);
+  o->step = b->step;
+  o->mass[0] = h[0];
+  o->mass[1] = h[1];
+  o->solute = h[2];
+  o->precipitate = h[3];
+  o->mass_removed[0] = h[4];
+  o->mass_removed[1] = h[5];
+  o->solute_removed = h[6];
+  o->n_solid = (int64_t)h[7];
+  o->nonfinite = h[8] > 0.0;
+  o->n_events = (int64_t)nev;
+  o->front_z = p.W > 0 ? h[OBS_SLOTS] : NAN;
+  o->delta_e = p.W > 0 ? h[OBS_SLOTS + 1] : 0.0;
+  o->closure_step = p.W > 0 ? (int64_t)h[OBS_SLOTS + 2] : -1;
+  if (o->nonfinite) {
+    b->poisoned = true;
+    return fail(LBM_ENONFINITE, "instance %d holds a NaN/Inf at step %lld", i, b->step);
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_fields(lbm_batch* b, int32_t i, uint32_t mask, double* host) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (i < 0 || i >= b->n || (mask && !host) || (mask >> 7)) return fail(LBM_EINVAL, "bad arguments");
+  const lbm_params& p = b->p[i];
+  const StepArgs& a = b->h_insts[2 * i + (int)(b->step & 1)];
+  const long long N = b->L[i].N;
+  double* stage = (double*)a.fout;  // idle buffer: rewritten by the next step before it is read
+  hipError_t e = launch_fields(a.fin, a.gin, a.mask, a.m, p.nx, p.ny, b->L[i].P,
+                               pending_bit(b->step - 1), b->L[i].solute, b->L[i].react, (float)p.G,
+                               (float)p.G_ads[0], (float)p.G_ads[1], (float)p.accel[0],
+                               (float)p.accel[1], stage, b->stream);
+  int k = 0;
+  for (int bit = 0; bit < 7 && e == hipSuccess; ++bit) {
+    if (!(mask & (1u << bit))) continue;
+    e = hipMemcpyAsync(host + (size_t)k * N, stage + (size_t)bit * N, N * sizeof(double),
+                       hipMemcpyDeviceToHost, b->stream);
+    ++k;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) { b->poisoned = true; return fail(LBM_EDEVICE, "batch fields: %s", hipGetErrorString(e)); }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_events(lbm_batch* b, int32_t i, int64_t first, lbm_event* buf, int64_t cap,
+                            int64_t* n) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (i < 0 || i >= b->n || !n || first < 0 || cap < 0 || (cap > 0 && !buf))
+    return fail(LBM_EINVAL, "bad events arguments");
+  const StepArgs& a = b->h_insts[2 * i];
+  unsigned long long nev = 0;
+  HIPCHECK(hipMemcpyAsync(&nev, a.ev_count, sizeof nev, hipMemcpyDeviceToHost, b->stream));
+  HIPCHECK(hipStreamSynchronize(b->stream));
+  *n = (int64_t)nev;
+  long long k = std::min<long long>(std::min<long long>((long long)nev, a.ev_cap) - first, cap);
+  if (k > 0) {
+    HIPCHECK(hipMemcpyAsync(buf, a.ev + first, k * sizeof(lbm_event), hipMemcpyDeviceToHost, b->stream));
+    HIPCHECK(hipStreamSynchronize(b->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* tx_out, int32_t* sy_out,
+                              double* best_ms) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+  if (b->step != 0) return fail(LBM_EINVAL, "batch autotune runs before the first step");
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  const int txs[] = {64, 128, 256};
+  const int sys[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 80};
+  int btx = b->tx, bsy = b->sy;
+  float best = 1e30f;
+  for (int tx : txs) {
+    for (int sy : sys) {
+      b->tx = tx;
+      b->sy = sy;
+      if ((st = batch_configure(b)) != LBM_OK) break;
+      if ((st = batch_launch(b, 2)) != LBM_OK) break;
+      float ms = 0;
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { st = fail(LBM_EDEVICE, "autotune event"); break; }
+      if ((st = batch_launch(b, steps)) != LBM_OK) break;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(LBM_EDEVICE, "autotune timing");
+        break;
+      }
+      if (ms < best) { best = ms; btx = tx; bsy = sy; }
+    }
+    if (st != LBM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LBM_OK) return st;
+  b->tx = btx;
+  b->sy = bsy;
+  if ((st = batch_configure(b)) != LBM_OK || (st = batch_reset(b)) != LBM_OK) return st;
+  if (tx_out) *tx_out = btx;
+  if (sy_out) *sy_out = bsy;
+  if (best_ms) *best_ms = best / steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_tile(const lbm_batch* b, int32_t* tx, int32_t* sy) {
+  if (!b || !tx || !sy) return fail(LBM_EINVAL, "NULL argument");
+  *tx = b->tx;
+  *sy = b->sy;
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
+}
+
+}  // extern "C"

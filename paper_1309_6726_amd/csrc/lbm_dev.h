@@ -42,6 +42,12 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const StepArgs& a, int tx, int arith64, hipStream_t st);
+hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
+                             const long long* stepc, int tx, int solute, int react, int arith64,
+                             hipStream_t st);
+hipError_t launch_front_batch(const StepArgs* insts, const int4* capi, const long long* stepc,
+                              int n, int slot, int nslots, double* table, hipStream_t st);
+int host_xcd_tile(int b, int T);
 hipError_t launch_init(const double* r1, const double* r2, const double* c, const uint8_t* mask,
                        float* f, float* g, double* m, int32_t* sstep, float* drop, long long N,
                        long long P, int solute, int react, hipStream_t st);

@@ -80,27 +80,12 @@ __device__ __forceinline__ void lds_barrier(int TX) {
 // memory round trip plus ~1 us of VALU work per wave, so resident waves are
 // what hides the memory latency.
 template <bool SOLUTE, bool REACT, typename R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
-k_step(const StepArgs a) {
-  extern __shared__ char lds_raw[];
+__device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
   const int TX = blockDim.x;
   R* s_r1 = (R*)lds_raw;                 // [4][TX] density of component 1 (0 at solid)
   R* s_r2 = s_r1 + 4 * TX;               // [4][TX] density of component 2
   float* s_s = (float*)(s_r2 + 4 * TX);  // [4][TX] solid flag 0/1
 
-  const int T = a.nstrips * a.nsegs;
-  const int b = blockIdx.x;
-  // XCD-aware order: the hardware hands block b to XCD b mod 8, so XCD x
-  // receives q + (x < r) blocks (q = T / 8, r = T mod 8).  Give each XCD a
-  // contiguous run of tiles, so vertically adjacent segments of a strip share
-  // one L2 and their halo rows are fetched from HBM once.
-  int tile = b;
-  if (a.remap) {
-    const int q = T >> 3, r = T & 7, x = b & 7, j = b >> 3;
-    tile = (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
-  }
-  const int strip = tile / a.nsegs;
-  const int seg = tile - strip * a.nsegs;
   const int t = threadIdx.x;
   const int nx = a.nx, ny = a.ny;
   const unsigned P = (unsigned)a.P;
@@ -330,6 +315,49 @@ k_step(const StepArgs a) {
   }
 }
 
+// XCD-aware order: the hardware hands block b to XCD b mod 8, so XCD x
+// receives q + (x < r) of T blocks (q = T / 8, r = T mod 8).  Give each XCD a
+// contiguous run of tiles, so vertically adjacent segments of a strip share
+// one L2 and their halo rows are fetched from HBM once.
+__host__ __device__ inline int xcd_tile(int b, int T) {
+  const int q = T >> 3, r = T & 7, x = b & 7, j = b >> 3;
+  return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
+template <bool SOLUTE, bool REACT, typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_step(const StepArgs a) {
+  extern __shared__ char lds_raw[];
+  const int T = a.nstrips * a.nsegs;
+  const int tile = a.remap ? xcd_tile(blockIdx.x, T) : (int)blockIdx.x;
+  const int strip = tile / a.nsegs;
+  step_tile<SOLUTE, REACT, R>(a, strip, tile - strip * a.nsegs, lds_raw);
+}
+
+// Batched step: one launch advances every instance of a batch by one step.
+// Block b takes tile tiles[b] (instance, strip, segment; the host orders the
+// list per XCD); the instance's arguments for the current parity come from
+// device memory, and the step index from the device counter, so a sequence of
+// launches can be captured once in a graph and replayed.
+template <bool SOLUTE, bool REACT, typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_step_batch(const StepArgs* __restrict__ insts, const int4* __restrict__ tiles,
+             const long long* __restrict__ stepc) {
+  extern __shared__ char lds_raw[];
+  const long long step = *stepc;
+  const int4 e = tiles[blockIdx.x];
+  StepArgs a = insts[2 * e.x + (int)(step & 1)];
+  a.step = step;
+  a.bit_prev = ((step - 1) & 1) ? 4u : 2u;
+  a.bit_cur = (step & 1) ? 4u : 2u;
+  step_tile<SOLUTE, REACT, R>(a, e.y, e.z, lds_raw);
+}
+
+// Advances the device step counter (a vector atomic, one lane).
+__global__ void k_tick(long long* stepc) {
+  if (threadIdx.x == 0) atomicAdd((unsigned long long*)stepc, 1ull);
+}
+
 // Rest-state populations from the FP64 densities (rounded once to FP32).
 __global__ void k_init(const double* __restrict__ rho1, const double* __restrict__ rho2,
                        const double* __restrict__ conc, const uint8_t* __restrict__ mask,
@@ -447,14 +475,13 @@ __device__ __forceinline__ void node_rho(const float* __restrict__ f, long long 
   *r2 = b;
 }
 
-// Capillary observables, one workgroup of 256 threads: centreline front,
-// largest grown width and first closure.  out: [0] z, [1] delta_e, [2] closure.
-__global__ void __launch_bounds__(256) k_obs_capillary(const float* __restrict__ f,
-                                                       const uint8_t* __restrict__ mask,
-                                                       const int32_t* __restrict__ sstep,
-                                                       int nx, long long P, unsigned bit_prev,
-                                                       int x_in, int x_out, int y0, int W,
-                                                       int react, double* __restrict__ out) {
+// Capillary observables computed by one workgroup of 256 threads: centreline
+// front, largest grown width and first closure.  out: [0] z, [1] delta_e,
+// [2] closure step (-1 if none).
+__device__ void capillary_obs(const float* __restrict__ f, const uint8_t* __restrict__ mask,
+                              const int32_t* __restrict__ sstep, int nx, long long P,
+                              unsigned bit_prev, int x_in, int x_out, int y0, int W, int react,
+                              double* __restrict__ out) {
   __shared__ int s_min[256];
   __shared__ double s_de[256];
   __shared__ long long s_cl[256];
@@ -546,6 +573,36 @@ __global__ void __launch_bounds__(256) k_obs_capillary(const float* __restrict__
   }
 }
 
+__global__ void __launch_bounds__(256) k_obs_capillary(const float* __restrict__ f,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const int32_t* __restrict__ sstep,
+                                                       int nx, long long P, unsigned bit_prev,
+                                                       int x_in, int x_out, int y0, int W,
+                                                       int react, double* __restrict__ out) {
+  capillary_obs(f, mask, sstep, nx, P, bit_prev, x_in, x_out, y0, W, react, out);
+}
+
+// Front of every instance of a batch (workgroup i -> instance i) into column
+// `slot` of the n x nslots table; queued without synchronisation.
+__global__ void __launch_bounds__(256) k_front_batch(const StepArgs* __restrict__ insts,
+                                                     const int4* __restrict__ capi,
+                                                     const long long* __restrict__ stepc,
+                                                     int slot, int nslots,
+                                                     double* __restrict__ table) {
+  __shared__ double res[3];
+  const long long step = *stepc;
+  const int i = blockIdx.x;
+  const StepArgs& a = insts[2 * i + (int)(step & 1)];
+  const int4 c = capi[i];  // x_in, x_out, y0, W
+  if (c.w <= 0) {
+    if (threadIdx.x == 0) table[(long long)i * nslots + slot] = __builtin_nan("");
+    return;
+  }
+  capillary_obs(a.fin, a.mask, a.sstep, a.nx, a.P, ((step - 1) & 1) ? 4u : 2u, c.x, c.y, c.z,
+                c.w, a.react, res);
+  if (threadIdx.x == 0) table[(long long)i * nslots + slot] = res[0];
+}
+
 // Macroscopic fields of the current state as FP64 planes:
 // 0 rho1, 1 rho2, 2 ux, 3 uy, 4 conc, 5 precipitate, 6 solid.
 __global__ void k_fields(const float* __restrict__ f, const float* __restrict__ g,
@@ -622,6 +679,37 @@ hipError_t launch_step(const StepArgs& a, int tx, int arith64, hipStream_t st) {
   }
   return hipGetLastError();
 }
+
+hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
+                             const long long* stepc, int tx, int solute, int react, int arith64,
+                             hipStream_t st) {
+  const size_t lds = (size_t)4 * tx * (2 * (arith64 ? sizeof(double) : sizeof(float)) + sizeof(float));
+  if (arith64) {
+    if (solute && react)
+      hipLaunchKernelGGL((k_step_batch<true, true, double>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    else if (solute)
+      hipLaunchKernelGGL((k_step_batch<true, false, double>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    else
+      hipLaunchKernelGGL((k_step_batch<false, false, double>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+  } else {
+    if (solute && react)
+      hipLaunchKernelGGL((k_step_batch<true, true, float>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    else if (solute)
+      hipLaunchKernelGGL((k_step_batch<true, false, float>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    else
+      hipLaunchKernelGGL((k_step_batch<false, false, float>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+  }
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, (long long*)stepc);
+  return hipGetLastError();
+}
+
+hipError_t launch_front_batch(const StepArgs* insts, const int4* capi, const long long* stepc,
+                              int n, int slot, int nslots, double* table, hipStream_t st) {
+  hipLaunchKernelGGL(k_front_batch, dim3(n), dim3(256), 0, st, insts, capi, stepc, slot, nslots, table);
+  return hipGetLastError();
+}
+
+int host_xcd_tile(int b, int T) { return xcd_tile(b, T); }
 
 hipError_t launch_init(const double* r1, const double* r2, const double* c, const uint8_t* mask,
                        float* f, float* g, double* m, int32_t* sstep, float* drop, long long N,

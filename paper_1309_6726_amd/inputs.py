@@ -372,3 +372,36 @@ def preform_problem(nx: int = 2048, ny: int = 2048, seed: int = 0, *,
 
 def config2(seed: int = 0) -> Problem:
     return preform_problem(seed=seed)
+
+
+# --------------------------------------------------------------------------
+# Parameter sweeps over uneven capillaries
+# --------------------------------------------------------------------------
+SWEEP_RANGES = {"W": (8, 64), "nx": (256, 2048), "log10_k": (-4.0, -2.0),
+                "theta": (20.0, 40.0), "threshold": (0.5, 2.0)}
+
+
+def sweep_params(seed: int, n: int) -> np.ndarray:
+    """n parameter rows (W, nx, k_r, theta_deg, threshold) for the capillary
+    sweep: W ~ U{8..64}, nx ~ U{256..2048}, k_r = 10^U[-4,-2],
+    theta ~ U[20, 40] degrees, threshold ~ U[0.5, 2.0].  Row i draws counters
+    5i..5i+4 of the seeded SplitMix64 stream."""
+    i = np.arange(n, dtype=np.uint64)
+    u = uniform53(seed, np.stack([5 * i + np.uint64(k) for k in range(5)]))
+    W = 8 + np.floor(u[0] * 57).astype(np.int64)
+    nx = 256 + np.floor(u[1] * 1793).astype(np.int64)
+    k = 10.0 ** (-4.0 + 2.0 * u[2])
+    th = 20.0 + 20.0 * u[3]
+    thr = 0.5 + 1.5 * u[4]
+    return np.stack([W, nx, k, th, thr], axis=1).astype(np.float64)
+
+
+def sweep_problem(row, instance: int, steps: int = 10_000) -> Problem:
+    """One reactive capillary of the sweep: ny = W + 12, the capillary layout,
+    D = 0.05, C0 = 1, adhesion from the contact angle, noise seed = instance."""
+    W, nx, k, th, thr = row
+    W, nx = int(W), int(nx)
+    return capillary_problem(nx, W + 12, W, seed=int(instance), k_r=float(k),
+                             threshold=float(thr), D=D_SOLUTE,
+                             G_ads=adhesion_for_angle(float(th)), steps=steps,
+                             name=f"sweep capillary {nx}x{W + 12} W={W}")

@@ -23,7 +23,11 @@ MAGIC = 0x4C424D5853494D31
 
 EXPORTS = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe", "lbm_fields",
            "lbm_events", "lbm_save", "lbm_load", "lbm_set_tile", "lbm_get_tile",
-           "lbm_autotune", "lbm_set_arith", "lbm_destroy", "lbm_strerror", "lbm_last_error")
+           "lbm_autotune", "lbm_set_arith", "lbm_destroy", "lbm_strerror", "lbm_last_error",
+           "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_set_tile",
+           "lbm_batch_get_tile", "lbm_batch_set_graph", "lbm_batch_step",
+           "lbm_batch_record_fronts", "lbm_batch_fronts", "lbm_batch_observe",
+           "lbm_batch_fields", "lbm_batch_events", "lbm_batch_autotune", "lbm_batch_destroy")
 
 
 class LbmError(RuntimeError):
@@ -94,6 +98,20 @@ def lib():
             "lbm_get_tile": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
             "lbm_autotune": [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_double)],
+            "lbm_batch_workspace_bytes": [C.c_int32, P, C.c_int32, C.POINTER(C.c_size_t)],
+            "lbm_batch_init": [C.c_int32, P, P, P, P, P, C.c_int32, P, P, C.c_size_t,
+                               C.POINTER(P)],
+            "lbm_batch_set_tile": [P, C.c_int32, C.c_int32],
+            "lbm_batch_get_tile": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+            "lbm_batch_set_graph": [P, C.c_int32],
+            "lbm_batch_step": [P, C.c_int64],
+            "lbm_batch_record_fronts": [P, C.c_int32],
+            "lbm_batch_fronts": [P, P],
+            "lbm_batch_observe": [P, C.c_int32, C.POINTER(Obs)],
+            "lbm_batch_fields": [P, C.c_int32, C.c_uint32, P],
+            "lbm_batch_events": [P, C.c_int32, C.c_int64, P, C.c_int64, C.POINTER(C.c_int64)],
+            "lbm_batch_autotune": [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_double)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -101,6 +119,8 @@ def lib():
             fn.restype = C.c_int
         L.lbm_destroy.argtypes = [P]
         L.lbm_destroy.restype = None
+        L.lbm_batch_destroy.argtypes = [P]
+        L.lbm_batch_destroy.restype = None
         L.lbm_strerror.argtypes = [C.c_int]
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_last_error.argtypes = []
@@ -254,3 +274,114 @@ def make_blob(p, f, solid, g=None, m=None, step: int = 0) -> bytes:
         parts.append(np.where(solid != 0, 0, -1).astype(np.int32).tobytes())
         parts.append(np.zeros(3 * N, dtype=np.float32).tobytes())
     return b"".join(parts)
+
+
+class Batch:
+    """Many lattices advanced together (one launch per step for all of them).
+    `problems`: sequence of objects with params, solid, rho1, rho2, conc."""
+
+    def __init__(self, problems, *, nslots=0, device="cuda:0", stream=None, tile=None,
+                 graph_chunk=0):
+        import torch
+        self.n = len(problems)
+        self.problems = list(problems)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nslots = int(nslots)
+        PA = Params * self.n
+        self._params = PA(*[Params.of(pr.params) for pr in problems])
+        n = C.c_size_t(0)
+        check(lib().lbm_batch_workspace_bytes(self.n, self._params, self.nslots, C.byref(n)))
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        self._arrays = []
+
+        def ptrs(get, dtype):
+            arr = (C.c_void_p * self.n)()
+            for i, pr in enumerate(problems):
+                a = get(pr)
+                if a is None:
+                    arr[i] = None
+                    continue
+                a = np.ascontiguousarray(a, dtype=dtype)
+                self._arrays.append(a)
+                arr[i] = a.ctypes.data
+            return arr
+
+        solid = ptrs(lambda pr: pr.solid, np.uint8)
+        r1 = ptrs(lambda pr: pr.rho1, np.float64)
+        r2 = ptrs(lambda pr: pr.rho2, np.float64)
+        conc = ptrs(lambda pr: pr.conc, np.float64)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().lbm_batch_init(self.n, self._params, solid, r1, r2, conc, self.nslots,
+                                       C.c_void_p(self.stream.cuda_stream), C.c_void_p(ws),
+                                       n.value, C.byref(h)))
+        self._arrays = []
+        self.h = h
+        if tile is not None:
+            self.set_tile(*tile)
+        if graph_chunk:
+            self.set_graph(graph_chunk)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tile(self, tx, sy):
+        check(lib().lbm_batch_set_tile(self.h, int(tx), int(sy)))
+
+    def tile(self):
+        a, b = C.c_int32(0), C.c_int32(0)
+        check(lib().lbm_batch_get_tile(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def set_graph(self, chunk):
+        check(lib().lbm_batch_set_graph(self.h, int(chunk)))
+
+    def step(self, n=1):
+        check(lib().lbm_batch_step(self.h, int(n)))
+
+    def record_fronts(self, slot):
+        check(lib().lbm_batch_record_fronts(self.h, int(slot)))
+
+    def fronts(self) -> np.ndarray:
+        out = np.zeros((self.n, self.nslots))
+        check(lib().lbm_batch_fronts(self.h, out.ctypes.data))
+        return out
+
+    def observe(self, i) -> dict:
+        o = Obs()
+        check(lib().lbm_batch_observe(self.h, int(i), C.byref(o)))
+        return o.as_dict()
+
+    def fields(self, i, names=FIELDS) -> dict:
+        pr = self.problems[i]
+        ny, nx = int(pr.params.ny), int(pr.params.nx)
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELDS.index(nm)
+        sel = [f for f in FIELDS if mask & (1 << FIELDS.index(f))]
+        buf = np.zeros((len(sel), ny, nx))
+        check(lib().lbm_batch_fields(self.h, int(i), mask, buf.ctypes.data))
+        return {nm: buf[k] for k, nm in enumerate(sel)}
+
+    def events(self, i) -> np.ndarray:
+        n = C.c_int64(0)
+        check(lib().lbm_batch_events(self.h, int(i), 0, None, 0, C.byref(n)))
+        buf = np.zeros(n.value, dtype=EVENT_DTYPE)
+        if n.value:
+            check(lib().lbm_batch_events(self.h, int(i), 0, buf.ctypes.data, n.value, C.byref(n)))
+        return buf
+
+    def autotune(self, steps=5):
+        a, b, ms = C.c_int32(0), C.c_int32(0), C.c_double(0)
+        check(lib().lbm_batch_autotune(self.h, int(steps), C.byref(a), C.byref(b), C.byref(ms)))
+        return (a.value, b.value), ms.value
