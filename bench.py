@@ -98,6 +98,35 @@ def cpu_baseline(prob, steps: int):
                       f"(after 1 untimed step), FP64, OpenMP {threads} threads, {dt:.1f} s"}
 
 
+def sweep_section(args, torch, dev):
+    """Reactive capillary sweep (uneven sizes and parameters): all runs in one
+    batch vs the same runs one after another with single-lattice handles."""
+    from paper_1309_6726_amd import inputs, sweep
+    rows = inputs.sweep_params(0, args.sweep_n)
+    probs = [inputs.sweep_problem(r, i, steps=args.sweep_steps) for i, r in enumerate(rows)]
+    nodes = sum(int(p.params.nx) * int(p.params.ny) for p in probs)
+    T = args.sweep_steps
+    fr_b, cl_b, sec_b, tile = sweep.run_batched(probs, T, 64, device=dev)
+    k = min(args.plain_sample, len(probs))
+    fr_p, cl_p, sec_p = sweep.run_plain(probs[:k], T, 64, device=dev)
+    same = bool(np.array_equal(fr_b[:k], fr_p) and np.array_equal(cl_b[:k], cl_p))
+    sample_nodes = sum(int(p.params.nx) * int(p.params.ny) for p in probs[:k])
+    # plain time per run, scaled from the sample to the whole sweep by node count
+    plain_total = sec_p * nodes / sample_nodes
+    return {"runs": len(probs), "steps_per_run": T, "nodes_total": nodes,
+            "sampler": "W~U{8..64}, nx~U{256..2048}, ny=W+12, k_r=10^U[-4,-2], "
+                       "theta~U[20,40] deg, threshold~U[0.5,2], seed 0",
+            "batched": {"seconds": round(sec_b, 3), "tile": list(tile), "graph_chunk": 156,
+                        "mlups": round(nodes * T / sec_b / 1e6, 1),
+                        "runs_per_hour": round(len(probs) / sec_b * 3600, 1)},
+            "plain": {"sample_runs": k, "sample_seconds": round(sec_p, 3),
+                      "mlups": round(sample_nodes * T / sec_p / 1e6, 1),
+                      "runs_per_hour": round(len(probs) / plain_total * 3600, 1)},
+            "batched_over_plain": round(plain_total / sec_b, 2),
+            "sample_results_identical": same,
+            "closed_runs": int(np.count_nonzero(cl_b >= 0))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +135,10 @@ def main():
     ap.add_argument("--tile", type=str, default="auto", help="TXxSY or auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the capillary sweep")
+    ap.add_argument("--sweep-n", type=int, default=512)
+    ap.add_argument("--sweep-steps", type=int, default=10000)
+    ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -197,6 +230,9 @@ def main():
                      "algorithmic_bytes_per_launch": int(per_launch),
                      "avg_launch_ms": round(ms_step, 5)},
     }
+    del sim
+    if not args.no_sweep:
+        out["sweep"] = sweep_section(args, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(out), flush=True)

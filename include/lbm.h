@@ -224,6 +224,47 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* tx, int32_t*
 
 void lbm_batch_destroy(lbm_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of the sweep: an MLP 5 -> 256 -> 256 -> 256 -> 65 (ReLU)
+ * mapping capillary width W, length L, reaction rate k_r, contact angle
+ * (degrees) and precipitation threshold to the centreline front z(t_j)/L at
+ * the 64 sample times t_j = ceil(j T / 64) and the pore-closure time / T (1 if
+ * no closure within T).  Inputs are normalised inside the library to [-1, 1]
+ * over the box [lo, hi] (log10 for k_r).  Dense layers run on the matrix cores
+ * (BF16 operands, FP32 accumulation) in forward and backward; training keeps
+ * FP32 master weights and uses Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * weighted mean-squared error.  Parameters are exchanged packed in FP32:
+ * W1 [256 x 5] row-major, b1 [256], W2 [256 x 256], b2, W3 [256 x 256], b3,
+ * W4 [65 x 256], b4 [65] (149,825 values).  The outputs are only meaningful
+ * inside the training box; callers check their queries against it and run
+ * the lattice Boltzmann model (lbm_batch_*) for the rest.
+ * ------------------------------------------------------------------------ */
+typedef struct surr_net surr_net;
+
+/* Workspace for minibatches / prediction chunks of up to max_batch rows and a
+ * resident training set of up to max_data samples. */
+lbm_status surr_workspace_bytes(int32_t max_batch, int32_t max_data, size_t* bytes);
+lbm_status surr_init(const double* lo, const double* hi, int32_t max_batch, int32_t max_data,
+                     void* stream, void* workspace, size_t ws_bytes, surr_net** out);
+/* Parameters (packed layout above); setting them clears the Adam state. */
+lbm_status surr_set_params(surr_net* s, const float* packed);
+lbm_status surr_get_params(surr_net* s, float* packed);
+/* Per-output weights of the loss (65 values, >= 0; default 1). */
+lbm_status surr_set_loss_weights(surr_net* s, const float* w);
+/* Training set x [n x 5] (raw inputs), y [n x 65] (targets), copied to HBM. */
+lbm_status surr_set_data(surr_net* s, const float* x, const float* y, int32_t n);
+/* One epoch over the resident set in the order perm (host, n indices):
+ * minibatches of `batch` rows, one Adam step each.  *mean_loss: mean of the
+ * minibatch losses (the only device-to-host transfer). */
+lbm_status surr_train_epoch(surr_net* s, const int32_t* perm, int32_t batch, float lr,
+                            double* mean_loss);
+/* Loss and packed parameter gradients for one batch (n <= max_batch), no update. */
+lbm_status surr_gradients(surr_net* s, const float* x, const float* y, int32_t n, float* grad,
+                          double* loss);
+/* y [n x 65] for x [n x 5] (host arrays). */
+lbm_status surr_predict(surr_net* s, const float* x, int32_t n, float* y);
+void surr_destroy(surr_net* s);
+
 void lbm_destroy(lbm_sim* sim);
 const char* lbm_strerror(lbm_status s);
 const char* lbm_last_error(void);

@@ -17,8 +17,7 @@
 
 using namespace lbmdev;
 
-namespace {
-
+namespace lbmdev {
 thread_local std::string g_err;
 
 lbm_status fail(lbm_status s, const char* fmt, ...) {
@@ -30,6 +29,9 @@ lbm_status fail(lbm_status s, const char* fmt, ...) {
   g_err = buf;
   return s;
 }
+}  // namespace lbmdev
+
+namespace {
 
 #define HIPCHECK(expr)                                                                  \
   do {                                                                                  \

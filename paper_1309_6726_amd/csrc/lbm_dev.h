@@ -41,6 +41,9 @@ struct StepArgs {
   double k_r, threshold;
 };
 
+// Records a message for lbm_last_error() and returns s.
+lbm_status fail(lbm_status s, const char* fmt, ...);
+
 hipError_t launch_step(const StepArgs& a, int tx, int arith64, hipStream_t st);
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
                              const long long* stepc, int tx, int solute, int react, int arith64,

@@ -405,3 +405,48 @@ def sweep_problem(row, instance: int, steps: int = 10_000) -> Problem:
                              threshold=float(thr), D=D_SOLUTE,
                              G_ads=adhesion_for_angle(float(th)), steps=steps,
                              name=f"sweep capillary {nx}x{W + 12} W={W}")
+
+
+# --------------------------------------------------------------------------
+# Surrogate of the sweep
+# --------------------------------------------------------------------------
+MLP_SIZES = (5, 256, 256, 256, 65)
+MLP_NPARAMS = sum(a * b + b for a, b in zip(MLP_SIZES[:-1], MLP_SIZES[1:]))  # 149,825
+
+
+def capillary_length(nx: int) -> int:
+    """L = x_out - x_in of the capillary layout (x_in = nx // 3, x_out = nx - 32)."""
+    return int(nx) - 32 - int(nx) // 3
+
+
+def surrogate_box():
+    """Normalisation / validity box of the surrogate inputs (W, L, k_r, theta,
+    threshold), i.e. the range of the sweep sampler."""
+    lo = np.array([8.0, capillary_length(256), 1e-4, 20.0, 0.5])
+    hi = np.array([64.0, capillary_length(2048), 1e-2, 40.0, 2.0])
+    return lo, hi
+
+
+def surrogate_inputs(rows: np.ndarray) -> np.ndarray:
+    """Sweep rows (W, nx, k_r, theta, threshold) -> surrogate inputs
+    (W, L, k_r, theta, threshold)."""
+    x = np.array(rows, dtype=np.float64).copy()
+    x[:, 1] = [capillary_length(v) for v in x[:, 1]]
+    return x
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)) from the seeded
+    SplitMix64 stream (one counter per weight, in packed order), zero biases.
+    Packed order: W1 [256 x 5], b1, W2, b2, W3, b3, W4 [65 x 256], b4."""
+    out = np.zeros(MLP_NPARAMS)
+    off = 0
+    ctr = 0
+    for fan_in, fan_out in zip(MLP_SIZES[:-1], MLP_SIZES[1:]):
+        nw = fan_in * fan_out
+        u = uniform53(seed, np.arange(ctr, ctr + nw, dtype=np.uint64))
+        ctr += nw
+        a = np.sqrt(6.0 / fan_in)
+        out[off:off + nw] = (2.0 * u - 1.0) * a
+        off += nw + fan_out
+    return out

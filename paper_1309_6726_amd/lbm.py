@@ -27,7 +27,10 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe", "lbm_fi
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_set_tile",
            "lbm_batch_get_tile", "lbm_batch_set_graph", "lbm_batch_step",
            "lbm_batch_record_fronts", "lbm_batch_fronts", "lbm_batch_observe",
-           "lbm_batch_fields", "lbm_batch_events", "lbm_batch_autotune", "lbm_batch_destroy")
+           "lbm_batch_fields", "lbm_batch_events", "lbm_batch_autotune", "lbm_batch_destroy",
+           "surr_workspace_bytes", "surr_init", "surr_set_params", "surr_get_params",
+           "surr_set_loss_weights", "surr_set_data", "surr_train_epoch", "surr_gradients",
+           "surr_predict", "surr_destroy")
 
 
 class LbmError(RuntimeError):
@@ -112,6 +115,15 @@ def lib():
             "lbm_batch_events": [P, C.c_int32, C.c_int64, P, C.c_int64, C.POINTER(C.c_int64)],
             "lbm_batch_autotune": [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double)],
+            "surr_workspace_bytes": [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+            "surr_init": [P, P, C.c_int32, C.c_int32, P, P, C.c_size_t, C.POINTER(P)],
+            "surr_set_params": [P, P],
+            "surr_get_params": [P, P],
+            "surr_set_loss_weights": [P, P],
+            "surr_set_data": [P, P, P, C.c_int32],
+            "surr_train_epoch": [P, P, C.c_int32, C.c_float, C.POINTER(C.c_double)],
+            "surr_gradients": [P, P, P, C.c_int32, P, C.POINTER(C.c_double)],
+            "surr_predict": [P, P, C.c_int32, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -121,6 +133,8 @@ def lib():
         L.lbm_destroy.restype = None
         L.lbm_batch_destroy.argtypes = [P]
         L.lbm_batch_destroy.restype = None
+        L.surr_destroy.argtypes = [P]
+        L.surr_destroy.restype = None
         L.lbm_strerror.argtypes = [C.c_int]
         L.lbm_strerror.restype = C.c_char_p
         L.lbm_last_error.argtypes = []

@@ -1,0 +1,202 @@
+"""Learned surrogate of the capillary sweep, trained on batched LB runs.
+
+The network (5 -> 256 -> 256 -> 256 -> 65) is trained and evaluated by the
+HIP kernels behind surr_* (include/lbm.h); this module marshals arguments and
+drives the pipeline:
+
+  * data: reactive capillary runs from the sweep sampler advanced by the
+    batched lattice Boltzmann path (front z(t_j) at t_j = ceil(j T / 64) and
+    the pore-closure step);
+  * targets: z(t_j) / S and closure / T (1 when not closed), where S is the
+    travel of the linear Washburn law, Eq. (1), at long times,
+    v T = gamma cos(theta) W T / (6 mu (L + L_e)), capped at L, plus 1 lu:
+    this makes every trajectory O(1) whatever its speed, so the loss tracks the
+    front error relative to the travel; the network learns the deviation from
+    the law (retardation by surface growth, pore closure, breakthrough);
+  * queries outside the training box go to the lattice Boltzmann model.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+
+import numpy as np
+
+from . import inputs, lbm, sweep
+
+GAMMA = 0.0761          # surface tension at G = 1.6 (Laplace calibration)
+MU = 1.0614 / 6.0       # dynamic viscosity: total density x (tau - 1/2) / 3
+ENTRANCE = 1.35         # entrance length in units of the width (Washburn runs)
+NSLOTS = 64
+
+
+def washburn_scale(x: np.ndarray, T: int) -> np.ndarray:
+    """S = min(v T, L) + 1 with v = gamma cos(theta) W / (6 mu (L + 1.35 W))."""
+    W, L, th = x[:, 0], x[:, 1], x[:, 3]
+    v = GAMMA * np.cos(np.radians(th)) * W / (6.0 * MU * (L + ENTRANCE * W))
+    return np.minimum(v * T, L) + 1.0
+
+
+def make_targets(x, fronts, closure, T):
+    S = washburn_scale(x, T)
+    z = fronts / S[:, None]
+    c = np.where(closure >= 0, closure / float(T), 1.0)
+    return np.concatenate([z, c[:, None]], axis=1).astype(np.float32)
+
+
+def decode(x, y, T):
+    """Network outputs -> (fronts in lattice units, closure step or -1)."""
+    S = washburn_scale(x, T)
+    fronts = y[:, :NSLOTS] * S[:, None]
+    L = x[:, 1]
+    fronts = np.clip(fronts, 0.0, L[:, None])
+    c = y[:, NSLOTS]
+    closure = np.where(c < 0.995, np.round(np.clip(c, 0, 1) * T), -1).astype(np.int64)
+    return fronts, closure
+
+
+def front_error(pred, true):
+    """Per run: RMS_j |z_hat_j - z_j| / max(z(T) - z(0), 1 lu), z(0) = 0."""
+    travel = np.maximum(true[:, -1], 1.0)
+    return np.sqrt(np.mean((pred - true) ** 2, axis=1)) / travel
+
+
+def in_box(x, lo, hi):
+    return np.all((x >= lo - 1e-9 * np.abs(lo)) & (x <= hi + 1e-9 * np.abs(hi)), axis=1)
+
+
+class Surrogate:
+    def __init__(self, max_batch=256, max_data=8192, *, device="cuda:0", stream=None):
+        import torch
+        self.lo, self.hi = inputs.surrogate_box()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L = lbm.lib()
+        n = C.c_size_t(0)
+        lbm.check(L.surr_workspace_bytes(int(max_batch), int(max_data), C.byref(n)))
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        lo = np.ascontiguousarray(self.lo, dtype=np.float64)
+        hi = np.ascontiguousarray(self.hi, dtype=np.float64)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            lbm.check(L.surr_init(lo.ctypes.data, hi.ctypes.data, int(max_batch), int(max_data),
+                                  C.c_void_p(self.stream.cuda_stream), C.c_void_p(ws), n.value,
+                                  C.byref(h)))
+        self.h = h
+        self.max_batch = int(max_batch)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lbm.lib().surr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == inputs.MLP_NPARAMS
+        lbm.check(lbm.lib().surr_set_params(self.h, a.ctypes.data))
+
+    def params(self):
+        a = np.zeros(inputs.MLP_NPARAMS, dtype=np.float32)
+        lbm.check(lbm.lib().surr_get_params(self.h, a.ctypes.data))
+        return a
+
+    def set_loss_weights(self, w):
+        a = np.ascontiguousarray(w, dtype=np.float32)
+        lbm.check(lbm.lib().surr_set_loss_weights(self.h, a.ctypes.data))
+
+    def set_data(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        self._n = x.shape[0]
+        lbm.check(lbm.lib().surr_set_data(self.h, x.ctypes.data, y.ctypes.data, self._n))
+
+    def train_epoch(self, perm, batch, lr):
+        p = np.ascontiguousarray(perm, dtype=np.int32)
+        loss = C.c_double(0)
+        lbm.check(lbm.lib().surr_train_epoch(self.h, p.ctypes.data, int(batch), float(lr),
+                                             C.byref(loss)))
+        return loss.value
+
+    def gradients(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        g = np.zeros(inputs.MLP_NPARAMS, dtype=np.float32)
+        loss = C.c_double(0)
+        lbm.check(lbm.lib().surr_gradients(self.h, x.ctypes.data, y.ctypes.data, x.shape[0],
+                                           g.ctypes.data, C.byref(loss)))
+        return loss.value, g
+
+    def predict(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.zeros((x.shape[0], inputs.MLP_SIZES[-1]), dtype=np.float32)
+        lbm.check(lbm.lib().surr_predict(self.h, x.ctypes.data, x.shape[0], y.ctypes.data))
+        return y
+
+
+def generate(seed: int, n: int, T: int, *, chunk: int = 512, device="cuda:0", log=None):
+    """n sweep runs (sampler seed) advanced by the batched LB path.
+    Returns (rows, x, fronts, closure, seconds)."""
+    rows = inputs.sweep_params(seed, n)
+    fronts = np.zeros((n, NSLOTS))
+    closure = np.zeros(n, dtype=np.int64)
+    t0 = time.perf_counter()
+    tile = None
+    for s in range(0, n, chunk):
+        probs = [inputs.sweep_problem(r, s + i, steps=T) for i, r in enumerate(rows[s:s + chunk])]
+        f, c, sec, tile = sweep.run_batched(probs, T, NSLOTS, tile=tile, autotune=tile is None,
+                                           device=device)
+        fronts[s:s + len(probs)] = f
+        closure[s:s + len(probs)] = c
+        if log:
+            log(f"  generated runs {s}..{s + len(probs) - 1} in {sec:.1f} s (tile {tile})")
+    return rows, inputs.surrogate_inputs(rows), fronts, closure, time.perf_counter() - t0
+
+
+def train(net: Surrogate, x, y, *, epochs=3000, batch=256, lr=2e-3, lr_min=2e-5, seed=0,
+          log=None, log_every=500):
+    """Adam with a cosine learning-rate schedule; permutations from the seeded
+    stream.  Returns the loss history (one value per logged epoch)."""
+    net.set_params(inputs.mlp_init_params(seed))
+    net.set_data(x, y)
+    n = x.shape[0]
+    hist = []
+    for e in range(epochs):
+        key = inputs.uniform53(seed + 1000003 * (e + 1), np.arange(n, dtype=np.uint64))
+        perm = np.argsort(key, kind="stable").astype(np.int32)
+        rate = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * e / max(1, epochs - 1)))
+        loss = net.train_epoch(perm, batch, rate)
+        if e % log_every == 0 or e == epochs - 1:
+            hist.append((e, loss))
+            if log:
+                log(f"  epoch {e}: loss {loss:.3e} lr {rate:.2e}")
+    return hist
+
+
+def predict_runs(net: Surrogate, rows, T: int, *, device="cuda:0"):
+    """Fronts and closure steps for sweep rows: the network inside its
+    training box, the batched lattice Boltzmann model outside it.
+    Returns (fronts, closure, in_box mask, lb_seconds)."""
+    x = inputs.surrogate_inputs(rows)
+    ok = in_box(x, net.lo, net.hi)
+    fronts = np.zeros((len(rows), NSLOTS))
+    closure = np.zeros(len(rows), dtype=np.int64)
+    if ok.any():
+        y = net.predict(x[ok])
+        f, c = decode(x[ok], y.astype(np.float64), T)
+        fronts[ok], closure[ok] = f, c
+    lb_sec = 0.0
+    if (~ok).any():
+        idx = np.nonzero(~ok)[0]
+        probs = [inputs.sweep_problem(rows[i], int(i), steps=T) for i in idx]
+        f, c, lb_sec, _ = sweep.run_batched(probs, T, NSLOTS, device=device)
+        fronts[idx], closure[idx] = f, c
+    return fronts, closure, ok, lb_sec

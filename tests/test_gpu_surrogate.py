@@ -1,0 +1,97 @@
+"""Surrogate MLP kernels (BF16 MFMA, FP32 accumulation) vs the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import parity as PT
+from oracle import mlp_oracle as M
+from paper_1309_6726_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def surr():
+    from paper_1309_6726_amd import surrogate as S
+    return S
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    lo, hi = inputs.surrogate_box()
+    x = lo + (hi - lo) * rng.uniform(size=(n, 5))
+    x[:, 2] = 10 ** rng.uniform(-4, -2, n)
+    t = rng.uniform(0, 1, (n, 65))
+    return x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_forward_matches_fp64_oracle(surr):
+    PT.say("[surrogate forward] 300 rows, chunks of 128")
+    net = surr.Surrogate(max_batch=128, max_data=16)
+    p = inputs.mlp_init_params(7).astype(np.float32)
+    p[1280:1536] = 0.02
+    net.set_params(p)
+    x, _ = _data(300, 1)
+    y = net.predict(x)
+    yo, _ = M.forward(p.astype(np.float64), x, net.lo, net.hi)
+    assert y.shape == (300, 65)
+    assert _rel(y, yo) <= 1e-2, _rel(y, yo)
+    assert np.abs(y - yo).max() <= 2e-2 * np.abs(yo).max()
+    back = net.params()
+    assert np.array_equal(back, p)
+
+
+def test_gradients_match_fp64_oracle(surr):
+    PT.say("[surrogate gradients] 200 rows")
+    net = surr.Surrogate(max_batch=256, max_data=16)
+    p = inputs.mlp_init_params(8).astype(np.float32)
+    net.set_params(p)
+    w = np.linspace(0.5, 2.0, 65).astype(np.float32)
+    net.set_loss_weights(w)
+    x, t = _data(200, 2)
+    loss, g = net.gradients(x, t)
+    lo_, go = M.loss_and_grad(p.astype(np.float64), x, t, net.lo, net.hi, w.astype(np.float64))
+    assert abs(loss - lo_) <= 1e-2 * lo_
+    off = 0
+    for fi, fo in zip(inputs.MLP_SIZES[:-1], inputs.MLP_SIZES[1:]):
+        for size in (fi * fo, fo):
+            a, b = g[off:off + size], go[off:off + size]
+            assert _rel(a, b) <= 2e-2, (fi, fo, size, _rel(a, b))
+            assert float(a @ b) / (np.linalg.norm(a) * np.linalg.norm(b)) > 0.999
+            off += size
+
+
+def test_adam_kernel_mirrors_oracle_adam(surr):
+    """Three training steps on one 64-row minibatch: the parameters equal the
+    oracle's Adam applied to the gradients the GPU reports for the same step."""
+    PT.say("[surrogate adam] 3 steps")
+    net = surr.Surrogate(max_batch=64, max_data=64)
+    p = inputs.mlp_init_params(9).astype(np.float32)
+    net.set_params(p)
+    x, t = _data(64, 3)
+    net.set_data(x, t)
+    po = p.astype(np.float64)
+    m = np.zeros_like(po)
+    v = np.zeros_like(po)
+    lr = 1e-3
+    ident = np.arange(64, dtype=np.int32)
+    for s in range(1, 4):
+        _, g = net.gradients(x, t)
+        po, m, v = M.adam_step(po, m, v, g.astype(np.float64), s, lr)
+        net.train_epoch(ident, 64, lr)
+        pg = net.params().astype(np.float64)
+        assert np.abs(pg - po).max() <= 1e-6 + 1e-5 * np.abs(po).max(), s
+
+
+def test_training_reduces_loss(surr):
+    PT.say("[surrogate training] smooth synthetic targets, 150 epochs")
+    net = surr.Surrogate(max_batch=128, max_data=1024)
+    x, _ = _data(1024, 4)
+    xn = M.normalise(x, net.lo, net.hi)
+    tt = np.stack([np.tanh(xn @ np.cos(np.arange(5) * (j + 1))) for j in range(65)], axis=1)
+    hist = surr.train(net, x, tt, epochs=150, batch=128, lr=2e-3, log_every=149)
+    assert hist[-1][1] < 0.1 * hist[0][1], hist
