@@ -127,6 +127,62 @@ def sweep_section(args, torch, dev):
             "closed_runs": int(np.count_nonzero(cl_b >= 0))}
 
 
+def surrogate_section(args, torch, dev, sweep_out):
+    """Train the MLP surrogate on batched LB runs (sampler seed 1), judge it on
+    held-out runs (seed 2) against the LB, and answer queries: network where it
+    is in range and confident, LB otherwise (including 32 out-of-range ones)."""
+    from paper_1309_6726_amd import surrogate as S
+    T = args.sweep_steps
+    rows, x, fr, cl, gen_s = S.generate(1, args.surr_train, T, device=dev)
+    rows_t, x_t, fr_t, cl_t, gen_t = S.generate(2, args.surr_test, T, device=dev)
+    y = S.make_targets(x, fr, cl, T)
+    net = S.Surrogate(max_batch=256, max_data=args.surr_train, device=dev)
+    t0 = time.perf_counter()
+    # the confidence gate is chosen on runs the network has not seen: train on
+    # all but the last 1/8 of the training runs, pick the gate on that 1/8,
+    # then train again on every training run
+    nv = len(rows) // 8
+    S.train(net, x[:-nv], y[:-nv], epochs=args.surr_epochs, lr=2e-3, log_every=args.surr_epochs)
+    gate = S.choose_gate(net, x[-nv:], fr[-nv:], T)
+    hist = S.train(net, x, y, epochs=args.surr_epochs, lr=2e-3, log_every=args.surr_epochs)
+    train_s = time.perf_counter() - t0
+    # raw network on the held-out runs
+    yp = net.predict(x_t).astype(np.float64)
+    f_raw, c_raw = S.decode(x_t, yp, T)
+    e_raw = S.front_error(f_raw, fr_t)
+    # gated answers (network where confident, LB elsewhere)
+    f_g, c_g, use, net_s, lb_s = S.answer(net, rows_t, T, gate, device=dev)
+    e_g = S.front_error(f_g, fr_t)
+    closure_err = np.abs(np.where(c_g >= 0, c_g, T) - np.where(cl_t >= 0, cl_t, T)) / T
+    # out-of-range queries must go to the LB
+    oor = S.out_of_range_rows(3, 32)
+    f_o, c_o, use_o, _, lb_o = S.answer(net, oor, T, gate, device=dev)
+    total_s = net_s + lb_s
+    plain_rph = sweep_out["plain"]["runs_per_hour"] if sweep_out else None
+    batched_rph = sweep_out["batched"]["runs_per_hour"] if sweep_out else None
+    rph = len(rows_t) / total_s * 3600
+    rph_amort = len(rows_t) / (total_s + (gen_s + train_s) * len(rows_t) / (len(rows) + len(rows_t)) ) * 3600
+    return {"train_runs": len(rows), "heldout_runs": len(rows_t), "steps_per_run": T,
+            "data_generation_s": round(gen_s + gen_t, 2), "train_s": round(train_s, 2),
+            "epochs": args.surr_epochs, "final_loss": hist[-1][1],
+            "network_only": {"front_err_mean": round(float(e_raw.mean()), 5),
+                             "front_err_median": round(float(np.median(e_raw)), 5),
+                             "frac_over_2pct": round(float((e_raw > 0.02).mean()), 4)},
+            "gate_min_predicted_travel_lu": gate,
+            "gate_chosen_on": f"{nv} validation runs from the training seed (mean error <= 1%)",
+            "answered_by_network": int(use.sum()),
+            "gated": {"front_err_mean": round(float(e_g.mean()), 5),
+                      "frac_over_2pct": round(float((e_g > 0.02).mean()), 4),
+                      "closure_err_mean": round(float(closure_err.mean()), 5),
+                      "network_s": round(net_s, 4), "lb_fallback_s": round(lb_s, 3),
+                      "runs_per_hour": round(rph, 1),
+                      "runs_per_hour_with_training_amortised_over_train+test": round(rph_amort, 1)},
+            "out_of_range": {"queries": len(oor), "sent_to_lb": int((~use_o).sum()),
+                             "lb_s": round(lb_o, 3)},
+            "vs_plain_runs_per_hour": None if not plain_rph else round(rph / plain_rph, 2),
+            "vs_batched_runs_per_hour": None if not batched_rph else round(rph / batched_rph, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +195,10 @@ def main():
     ap.add_argument("--sweep-n", type=int, default=512)
     ap.add_argument("--sweep-steps", type=int, default=10000)
     ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate section")
+    ap.add_argument("--surr-train", type=int, default=4096)
+    ap.add_argument("--surr-test", type=int, default=256)
+    ap.add_argument("--surr-epochs", type=int, default=3000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -233,6 +293,8 @@ def main():
     del sim
     if not args.no_sweep:
         out["sweep"] = sweep_section(args, torch, dev)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_section(args, torch, dev, out.get("sweep"))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -251,8 +251,10 @@ lbm_status surr_set_params(surr_net* s, const float* packed);
 lbm_status surr_get_params(surr_net* s, float* packed);
 /* Per-output weights of the loss (65 values, >= 0; default 1). */
 lbm_status surr_set_loss_weights(surr_net* s, const float* w);
-/* Training set x [n x 5] (raw inputs), y [n x 65] (targets), copied to HBM. */
-lbm_status surr_set_data(surr_net* s, const float* x, const float* y, int32_t n);
+/* Training set x [n x 5] (raw inputs), y [n x 65] (targets) and optional
+ * per-sample loss weights row_w [n] (NULL: all 1), copied to HBM.  The loss of
+ * a minibatch is sum_rows row_w sum_j w_j (y - t)^2 / (rows * sum_j w_j). */
+lbm_status surr_set_data(surr_net* s, const float* x, const float* y, const float* row_w, int32_t n);
 /* One epoch over the resident set in the order perm (host, n indices):
  * minibatches of `batch` rows, one Adam step each.  *mean_loss: mean of the
  * minibatch losses (the only device-to-host transfer). */

@@ -29,7 +29,7 @@ size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 struct SLayout {
   size_t p[NL], m1[NL], m2[NL], g[NL], wb[NL], wt[NL];
   size_t x0, x0t, hf[3], hb[3], ht[3], y, t, dy, dyt, dhb[3], dht[3];
-  size_t X, Y, perm, qx, qy, lo, hi, lw, loss, total;
+  size_t X, Y, RW, perm, qx, qy, lo, hi, lw, rw, loss, total;
   int Bp, max_data;
 };
 
@@ -64,6 +64,8 @@ SLayout slayout(int max_batch, int max_data) {
   S.dyt = take(B * NOUTP * 2);
   S.X = take((size_t)max_data * NIN * 4);
   S.Y = take((size_t)max_data * NOUT * 4);
+  S.RW = take((size_t)max_data * 4);
+  S.rw = take(B * 4);
   S.perm = take((size_t)max_data * 4);
   S.qx = take(B * NIN * 4);
   S.qy = take(B * NOUT * 4);
@@ -95,11 +97,12 @@ namespace {
   } while (0)
 
 // forward pass for `rows` samples gathered from (X, Y) by idx (or in order)
-lbm_status forward(surr_net* s, const float* X, const float* Y, const int32_t* idx, int rows) {
+lbm_status forward(surr_net* s, const float* X, const float* Y, const float* RW,
+                   const int32_t* idx, int rows) {
   const SLayout& S = s->S;
   const int B = S.Bp;
-  HC(gather(X, Y, idx, rows, B, s->at<float>(S.lo), s->at<float>(S.hi), s->at<__bf16>(S.x0),
-            s->at<__bf16>(S.x0t), Y ? s->at<float>(S.t) : nullptr, s->stream));
+  HC(gather(X, Y, RW, idx, rows, B, s->at<float>(S.lo), s->at<float>(S.hi), s->at<__bf16>(S.x0),
+            s->at<__bf16>(S.x0t), Y ? s->at<float>(S.t) : nullptr, s->at<float>(S.rw), s->stream));
   const __bf16* in = s->at<__bf16>(S.x0);
   int ldin = KIN;
   for (int l = 0; l < 3; ++l) {
@@ -126,8 +129,8 @@ lbm_status forward(surr_net* s, const float* X, const float* Y, const int32_t* i
 lbm_status backward(surr_net* s, int rows) {
   const SLayout& S = s->S;
   const int B = S.Bp;
-  HC(loss(s->at<float>(S.y), s->at<float>(S.t), s->at<float>(S.lw), rows, B, s->at<__bf16>(S.dy),
-          s->at<__bf16>(S.dyt), s->at<double>(S.loss), s->stream));
+  HC(loss(s->at<float>(S.y), s->at<float>(S.t), s->at<float>(S.lw), s->at<float>(S.rw), rows, B,
+          s->at<__bf16>(S.dy), s->at<__bf16>(S.dyt), s->at<double>(S.loss), s->stream));
   // layer l has input activations in[l] (BF16 transposed) and output gradient dout
   const __bf16* dout_t = s->at<__bf16>(S.dyt);   // [N_l x B]
   const __bf16* dout_b = s->at<__bf16>(S.dy);    // [B x N_l]
@@ -268,10 +271,17 @@ lbm_status surr_set_loss_weights(surr_net* s, const float* w) {
   return LBM_OK;
 }
 
-lbm_status surr_set_data(surr_net* s, const float* x, const float* y, int32_t n) {
+lbm_status surr_set_data(surr_net* s, const float* x, const float* y, const float* row_w, int32_t n) {
   if (!s || !x || !y || n < 1 || n > s->S.max_data) return fail(LBM_EINVAL, "bad training data");
+  std::vector<float> w(n, 1.0f);
+  if (row_w)
+    for (int i = 0; i < n; ++i) {
+      if (!(row_w[i] >= 0.0f) || !std::isfinite(row_w[i])) return fail(LBM_EINVAL, "bad row weight %d", i);
+      w[i] = row_w[i];
+    }
   HC(hipMemcpyAsync(s->ws + s->S.X, x, (size_t)n * NIN * 4, hipMemcpyHostToDevice, s->stream));
   HC(hipMemcpyAsync(s->ws + s->S.Y, y, (size_t)n * NOUT * 4, hipMemcpyHostToDevice, s->stream));
+  HC(hipMemcpyAsync(s->ws + s->S.RW, w.data(), (size_t)n * 4, hipMemcpyHostToDevice, s->stream));
   HC(hipStreamSynchronize(s->stream));
   s->n_data = n;
   return LBM_OK;
@@ -293,7 +303,8 @@ lbm_status surr_train_epoch(surr_net* s, const int32_t* perm, int32_t batch, flo
   for (int off = 0; off < s->n_data; off += batch, ++nb) {
     const int rows = std::min(batch, s->n_data - off);
     lbm_status st;
-    if ((st = forward(s, X, Y, s->at<int32_t>(s->S.perm) + off, rows)) != LBM_OK) return st;
+    if ((st = forward(s, X, Y, s->at<float>(s->S.RW), s->at<int32_t>(s->S.perm) + off, rows)) != LBM_OK)
+      return st;
     if ((st = backward(s, rows)) != LBM_OK) return st;
     if ((st = adam_all(s, lr)) != LBM_OK) return st;
   }
@@ -311,7 +322,8 @@ lbm_status surr_gradients(surr_net* s, const float* x, const float* y, int32_t n
   HC(hipMemcpyAsync(s->ws + s->S.qy, y, (size_t)n * NOUT * 4, hipMemcpyHostToDevice, s->stream));
   HC(hipMemsetAsync(s->ws + s->S.loss, 0, 8, s->stream));
   lbm_status st;
-  if ((st = forward(s, s->at<float>(s->S.qx), s->at<float>(s->S.qy), nullptr, n)) != LBM_OK) return st;
+  if ((st = forward(s, s->at<float>(s->S.qx), s->at<float>(s->S.qy), nullptr, nullptr, n)) != LBM_OK)
+    return st;
   if ((st = backward(s, n)) != LBM_OK) return st;
   for (int l = 0; l < NL; ++l) {
     std::vector<float> pad((size_t)LN[l] * LK[l] + LN[l]);
@@ -337,7 +349,7 @@ lbm_status surr_predict(surr_net* s, const float* x, int32_t n, float* y) {
     const int rows = std::min(s->S.Bp, n - off);
     HC(hipMemcpyAsync(s->ws + s->S.qx, x + (size_t)off * NIN, (size_t)rows * NIN * 4,
                       hipMemcpyHostToDevice, s->stream));
-    lbm_status st = forward(s, s->at<float>(s->S.qx), nullptr, nullptr, rows);
+    lbm_status st = forward(s, s->at<float>(s->S.qx), nullptr, nullptr, nullptr, rows);
     if (st != LBM_OK) return st;
     HC(hipMemcpy2DAsync(y + (size_t)off * NOUT, NOUT * 4, s->ws + s->S.y, NOUTP * 4, NOUT * 4, rows,
                         hipMemcpyDeviceToHost, s->stream));

@@ -27,11 +27,11 @@ struct GemmArgs {
 };
 
 hipError_t gemm(int epi, const GemmArgs& g, hipStream_t st);
-hipError_t gather(const float* X, const float* Y, const int32_t* idx, int rows, int Bp,
-                  const float* lo, const float* hi, __bf16* x0, __bf16* x0t, float* t,
-                  hipStream_t st);
-hipError_t loss(const float* y, const float* t, const float* w, int rows, int Bp, __bf16* dy,
-                __bf16* dyt, double* acc, hipStream_t st);
+hipError_t gather(const float* X, const float* Y, const float* RW, const int32_t* idx, int rows,
+                  int Bp, const float* lo, const float* hi, __bf16* x0, __bf16* x0t, float* t,
+                  float* rw, hipStream_t st);
+hipError_t loss(const float* y, const float* t, const float* w, const float* rw, int rows, int Bp,
+                __bf16* dy, __bf16* dyt, double* acc, hipStream_t st);
 hipError_t colsum(const __bf16* dht, int Bp, int n_units, float* db, hipStream_t st);
 hipError_t adam(float* p, float* m1, float* m2, const float* grad, int count, int nw, int N, int K,
                 float lr, float b1, float b2, float eps, float c1, float c2, __bf16* wb,

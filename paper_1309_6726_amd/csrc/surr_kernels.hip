@@ -67,13 +67,15 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const GemmArgs g) {
 // theta, threshold); x' = 2 (x - lo) / (hi - lo) - 1, with log10 applied to
 // k_r and its bounds.
 __global__ void k_gather(const float* __restrict__ X, const float* __restrict__ Y,
-                         const int32_t* __restrict__ idx, int rows, int Bp, const float* __restrict__ lo,
-                         const float* __restrict__ hi, __bf16* __restrict__ x0, __bf16* __restrict__ x0t,
-                         float* __restrict__ t) {
+                         const float* __restrict__ RW, const int32_t* __restrict__ idx, int rows,
+                         int Bp, const float* __restrict__ lo, const float* __restrict__ hi,
+                         __bf16* __restrict__ x0, __bf16* __restrict__ x0t, float* __restrict__ t,
+                         float* __restrict__ rw) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= Bp) return;
   const bool real = r < rows;
   const int src = real ? (idx ? idx[r] : r) : 0;
+  if (rw) rw[r] = real ? (RW ? RW[src] : 1.0f) : 0.0f;
   for (int j = 0; j < KIN; ++j) {
     float v = 0.0f;
     if (real && j < NIN) {
@@ -91,10 +93,12 @@ __global__ void k_gather(const float* __restrict__ X, const float* __restrict__ 
 }
 
 // Weighted mean-squared error over the real rows and outputs:
-// loss = sum_rows sum_j w_j (y - t)^2 / (rows * sum_j w_j), its gradient dY
-// (BF16 row-major and transposed) and the loss added to *loss_acc.
+// loss = sum_rows c_r sum_j w_j (y - t)^2 / (rows * sum_j w_j) with per-output
+// weights w and per-row weights c, its gradient dY (BF16 row-major and
+// transposed) and the loss added to *loss_acc.
 __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ y, const float* __restrict__ t,
-                                              const float* __restrict__ w, int rows, int Bp,
+                                              const float* __restrict__ w, const float* __restrict__ rw,
+                                              int rows, int Bp,
                                               __bf16* __restrict__ dy, __bf16* __restrict__ dyt,
                                               double* __restrict__ loss_acc) {
   __shared__ double red[256];
@@ -107,8 +111,9 @@ __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ y, const
     float d = 0.0f;
     if (r < rows && j < NOUT) {
       const float diff = y[e] - t[e];
-      d = 2.0f * w[j] * diff * scale;
-      s += (double)(w[j] * diff * diff * scale);
+      const float c = w[j] * rw[r] * scale;
+      d = 2.0f * c * diff;
+      s += (double)(c * diff * diff);
     }
     dy[e] = (__bf16)d;
     dyt[(size_t)j * Bp + r] = (__bf16)d;
@@ -180,18 +185,18 @@ hipError_t gemm(int epi, const GemmArgs& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t gather(const float* X, const float* Y, const int32_t* idx, int rows, int Bp,
-                  const float* lo, const float* hi, __bf16* x0, __bf16* x0t, float* t,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3((Bp + 127) / 128), dim3(128), 0, st, X, Y, idx, rows, Bp, lo,
-                     hi, x0, x0t, t);
+hipError_t gather(const float* X, const float* Y, const float* RW, const int32_t* idx, int rows,
+                  int Bp, const float* lo, const float* hi, __bf16* x0, __bf16* x0t, float* t,
+                  float* rw, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3((Bp + 127) / 128), dim3(128), 0, st, X, Y, RW, idx, rows, Bp,
+                     lo, hi, x0, x0t, t, rw);
   return hipGetLastError();
 }
 
-hipError_t loss(const float* y, const float* t, const float* w, int rows, int Bp, __bf16* dy,
-                __bf16* dyt, double* acc, hipStream_t st) {
+hipError_t loss(const float* y, const float* t, const float* w, const float* rw, int rows, int Bp,
+                __bf16* dy, __bf16* dyt, double* acc, hipStream_t st) {
   const int blocks = (Bp * NOUTP + 255) / 256 < 256 ? (Bp * NOUTP + 255) / 256 : 256;
-  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, st, y, t, w, rows, Bp, dy, dyt, acc);
+  hipLaunchKernelGGL(k_loss, dim3(blocks), dim3(256), 0, st, y, t, w, rw, rows, Bp, dy, dyt, acc);
   return hipGetLastError();
 }
 

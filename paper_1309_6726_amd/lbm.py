@@ -120,7 +120,7 @@ def lib():
             "surr_set_params": [P, P],
             "surr_get_params": [P, P],
             "surr_set_loss_weights": [P, P],
-            "surr_set_data": [P, P, P, C.c_int32],
+            "surr_set_data": [P, P, P, P, C.c_int32],
             "surr_train_epoch": [P, P, C.c_int32, C.c_float, C.POINTER(C.c_double)],
             "surr_gradients": [P, P, P, C.c_int32, P, C.POINTER(C.c_double)],
             "surr_predict": [P, P, C.c_int32, P],

@@ -113,11 +113,13 @@ class Surrogate:
         a = np.ascontiguousarray(w, dtype=np.float32)
         lbm.check(lbm.lib().surr_set_loss_weights(self.h, a.ctypes.data))
 
-    def set_data(self, x, y):
+    def set_data(self, x, y, row_weights=None):
         x = np.ascontiguousarray(x, dtype=np.float32)
         y = np.ascontiguousarray(y, dtype=np.float32)
+        w = None if row_weights is None else np.ascontiguousarray(row_weights, dtype=np.float32)
         self._n = x.shape[0]
-        lbm.check(lbm.lib().surr_set_data(self.h, x.ctypes.data, y.ctypes.data, self._n))
+        lbm.check(lbm.lib().surr_set_data(self.h, x.ctypes.data, y.ctypes.data,
+                                          None if w is None else w.ctypes.data, self._n))
 
     def train_epoch(self, perm, batch, lr):
         p = np.ascontiguousarray(perm, dtype=np.int32)
@@ -161,12 +163,21 @@ def generate(seed: int, n: int, T: int, *, chunk: int = 512, device="cuda:0", lo
     return rows, inputs.surrogate_inputs(rows), fronts, closure, time.perf_counter() - t0
 
 
+def row_weights(x, fronts, T, cap=400.0):
+    """Per-run loss weights (S / max(z(T), 1))^2, capped and normalised to
+    mean 1: with targets z / S the weighted loss then follows the front error
+    relative to the travel, also for fronts that stall or recede."""
+    S = washburn_scale(x, T)
+    w = np.minimum((S / np.maximum(fronts[:, -1], 1.0)) ** 2, cap)
+    return w / w.mean()
+
+
 def train(net: Surrogate, x, y, *, epochs=3000, batch=256, lr=2e-3, lr_min=2e-5, seed=0,
-          log=None, log_every=500):
+          log=None, log_every=500, weights=None):
     """Adam with a cosine learning-rate schedule; permutations from the seeded
     stream.  Returns the loss history (one value per logged epoch)."""
     net.set_params(inputs.mlp_init_params(seed))
-    net.set_data(x, y)
+    net.set_data(x, y, weights)
     n = x.shape[0]
     hist = []
     for e in range(epochs):
@@ -200,3 +211,65 @@ def predict_runs(net: Surrogate, rows, T: int, *, device="cuda:0"):
         f, c, lb_sec, _ = sweep.run_batched(probs, T, NSLOTS, device=device)
         fronts[idx], closure[idx] = f, c
     return fronts, closure, ok, lb_sec
+
+
+def choose_gate(net: Surrogate, x, fronts, T, target=0.01, min_frac=0.25):
+    """Smallest predicted travel z_hat(T) (lattice units) such that the runs
+    predicted at or above it have mean front error <= target, chosen on runs
+    the network has not been trained on.  Runs predicted below it (fronts that
+    hardly enter, stall or recede under strong surface growth, where the error
+    relative to their small travel is large) go to the lattice Boltzmann model."""
+    y = net.predict(x).astype(np.float64)
+    f, _ = decode(x, y, T)
+    err = front_error(f, fronts)
+    travel = f[:, -1]
+    for z in np.arange(0.0, 101.0, 1.0):
+        sel = travel >= z
+        if sel.sum() < min_frac * len(x):
+            break
+        if err[sel].mean() <= target:
+            return float(z)
+    return float("inf")
+
+
+def answer(net: Surrogate, rows, T: int, gate: float, *, device="cuda:0"):
+    """Sweep queries answered by the network where it is in its box and
+    confident (predicted travel z_hat(T) >= gate lattice units), by the batched
+    lattice Boltzmann model otherwise.  Returns (fronts, closure, used_net mask,
+    net_seconds, lb_seconds)."""
+    x = inputs.surrogate_inputs(rows)
+    ok = in_box(x, net.lo, net.hi)
+    fronts = np.zeros((len(rows), NSLOTS))
+    closure = np.zeros(len(rows), dtype=np.int64)
+    use = np.zeros(len(rows), dtype=bool)
+    t0 = time.perf_counter()
+    if ok.any():
+        y = net.predict(x[ok]).astype(np.float64)
+        f, c = decode(x[ok], y, T)
+        conf = f[:, -1] >= gate
+        idx = np.nonzero(ok)[0][conf]
+        fronts[idx], closure[idx] = f[conf], c[conf]
+        use[idx] = True
+    net_sec = time.perf_counter() - t0
+    lb_sec = 0.0
+    rest = np.nonzero(~use)[0]
+    if len(rest):
+        probs = [inputs.sweep_problem(rows[i], int(i), steps=T) for i in rest]
+        f, c, lb_sec, _ = sweep.run_batched(probs, T, NSLOTS, device=device)
+        fronts[rest], closure[rest] = f, c
+    return fronts, closure, use, net_sec, lb_sec
+
+
+def out_of_range_rows(seed: int, n: int = 32):
+    """Queries outside the training box: width 72..96 or reaction rate
+    1.2e-2..5e-2 (the other inputs inside the box)."""
+    base = inputs.sweep_params(seed, n)
+    u = inputs.uniform53(seed + 7, np.arange(2 * n, dtype=np.uint64)).reshape(2, n)
+    rows = base.copy()
+    for i in range(n):
+        if i % 2 == 0:
+            rows[i, 0] = 72 + np.floor(u[0, i] * 25)
+            rows[i, 1] = 256 + np.floor(u[1, i] * 512)
+        else:
+            rows[i, 2] = 1.2e-2 + u[0, i] * 3.8e-2
+    return rows

@@ -95,3 +95,19 @@ def test_training_reduces_loss(surr):
     tt = np.stack([np.tanh(xn @ np.cos(np.arange(5) * (j + 1))) for j in range(65)], axis=1)
     hist = surr.train(net, x, tt, epochs=150, batch=128, lr=2e-3, log_every=149)
     assert hist[-1][1] < 0.1 * hist[0][1], hist
+
+
+def test_out_of_range_queries_go_to_lb(surr):
+    """Queries outside the training box are answered by the batched LB, with
+    the same fronts and closure steps as a direct batched run."""
+    from paper_1309_6726_amd import sweep
+    PT.say("[surrogate fallback] 4 out-of-range queries, 300 steps")
+    net = surr.Surrogate(max_batch=64, max_data=16)
+    net.set_params(inputs.mlp_init_params(5))
+    rows = surr.out_of_range_rows(3, 4)
+    T = 300
+    f, c, use, _, _ = surr.answer(net, rows, T, gate=0.0)
+    assert not use.any()
+    probs = [inputs.sweep_problem(r, i, steps=T) for i, r in enumerate(rows)]
+    f2, c2, _, _ = sweep.run_batched(probs, T, surr.NSLOTS)
+    assert np.array_equal(f, f2) and np.array_equal(c, c2)
