@@ -166,7 +166,11 @@ lbm_status lbm_get_tile(const lbm_sim* sim, int32_t* tx, int32_t* sy);
 lbm_status lbm_set_arith(lbm_sim* sim, int32_t bits);
 
 /* Time the launch shapes (steps_per_candidate steps each, on a saved copy of
- * the state, which is restored), keep the fastest and report it. */
+ * the state, which is restored), keep the fastest and report it.  When the
+ * environment variable LBM_AUTOTUNE_CACHE names a file, a cached choice for
+ * the same (GPU architecture, nx x ny, solute/reaction switches, arithmetic)
+ * is used without timing, and new choices are appended to it as JSON lines
+ * {"key": ..., "tx": ..., "sy": ..., "ms": ...}. */
 lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_candidate, int32_t* tx, int32_t* sy,
                         double* best_ms_per_step);
 

@@ -514,10 +514,72 @@ lbm_status lbm_get_tile(const lbm_sim* s, int32_t* tx, int32_t* sy) {
   return LBM_OK;
 }
 
+namespace {
+
+// Autotune cache: a JSON-lines file named by LBM_AUTOTUNE_CACHE, one object
+// per line {"key": "<arch>:<nx>x<ny>:<flags>:<arith>", "tx": .., "sy": .., "ms": ..}.
+std::string tune_key(const lbm_sim* s) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  char arch[64] = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char* c = arch; *c; ++c)
+      if (*c == ':' || *c == '"' || *c == ' ') *c = '_';
+  }
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s:%dx%d:%d:%d", arch, s->p.nx, s->p.ny,
+           (s->L.solute ? 1 : 0) | (s->L.react ? 2 : 0), s->arith64 ? 64 : 32);
+  return buf;
+}
+
+bool tune_lookup(const std::string& key, int* tx, int* sy, double* ms) {
+  const char* path = getenv("LBM_AUTOTUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* fh = fopen(path, "r");
+  if (!fh) return false;
+  char line[512], k[256];
+  bool found = false;
+  while (fgets(line, sizeof line, fh)) {
+    int a = 0, b = 0;
+    double m = 0;
+    if (sscanf(line, " {\"key\": \"%255[^\"]\", \"tx\": %d, \"sy\": %d, \"ms\": %lf", k, &a, &b, &m) == 4 &&
+        key == k && tile_ok(a, b)) {
+      *tx = a; *sy = b; *ms = m;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  fclose(fh);
+  return found;
+}
+
+void tune_store(const std::string& key, int tx, int sy, double ms) {
+  const char* path = getenv("LBM_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fh = fopen(path, "a");
+  if (!fh) return;
+  fprintf(fh, "{\"key\": \"%s\", \"tx\": %d, \"sy\": %d, \"ms\": %.6f}\n", key.c_str(), tx, sy, ms);
+  fclose(fh);
+}
+
+}  // namespace
+
 lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_out, double* best_ms) {
   lbm_status st = guard(s);
   if (st != LBM_OK) return st;
   if (steps < 1) return fail(LBM_EINVAL, "steps_per_candidate must be >= 1");
+  {
+    int ctx = 0, csy = 0;
+    double cms = 0;
+    if (tune_lookup(tune_key(s), &ctx, &csy, &cms)) {
+      s->tx = ctx;
+      s->sy = csy;
+      if (tx_out) *tx_out = ctx;
+      if (sy_out) *sy_out = csy;
+      if (best_ms) *best_ms = cms;
+      return LBM_OK;
+    }
+  }
   size_t n = 0;
   if ((st = lbm_save(s, nullptr, 0, &n)) != LBM_OK) return st;
   std::vector<char> blob;
@@ -555,6 +617,7 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   if ((st = lbm_load(s, blob.data(), n)) != LBM_OK) return st;
   s->tx = btx;
   s->sy = bsy;
+  tune_store(tune_key(s), btx, bsy, best / steps);
   if (tx_out) *tx_out = btx;
   if (sy_out) *sy_out = bsy;
   if (best_ms) *best_ms = best / steps;

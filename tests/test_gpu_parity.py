@@ -293,3 +293,20 @@ def test_error_paths(lbm):
     sim.load(blob)          # a good checkpoint clears the poisoned state
     sim.step(5)
     assert sim.observe()["step"] == 15
+
+
+def test_autotune_cache(lbm, tmp_path, monkeypatch):
+    """With LBM_AUTOTUNE_CACHE set, the first autotune times and records its
+    choice; a second handle of the same lattice reuses it without timing."""
+    path = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(path))
+    prob = inputs.config0()
+    PT.say("[autotune cache]")
+    a = lbm.Sim.from_problem(prob)
+    (tx, sy), ms = a.autotune(steps=2)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and f'"tx": {tx}, "sy": {sy}' in lines[0]
+    b = lbm.Sim.from_problem(prob)
+    assert b.autotune(steps=2)[0] == (tx, sy)
+    assert len(path.read_text().splitlines()) == 1
+    assert b.tile() == (tx, sy)
