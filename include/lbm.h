@@ -144,18 +144,23 @@ lbm_status lbm_events(lbm_sim* sim, int64_t first, lbm_event* buf, int64_t cap, 
  * size needed.  lbm_load restores a blob written by lbm_save for a handle with
  * the same parameters; it also clears a poisoned state.  Blob layout (native
  * endianness, no padding): header {uint64 magic 0x4C424D5853494D31, int32 nx,
- * ny, int32 flags (1 solute, 2 reaction), int32 version 1, int64 step,
+ * ny, int32 flags (1 solute, 2 reaction), int32 version 2, int64 step,
  * int64 n_events}, then f float[18][N] (component-major, link order e0..e8 =
  * (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)), g float[5][N]
- * if solute, mask uint8[N] (bit0 solid, bit1/bit2 growth pending), then if
+ * if solute, mask uint8[N] (bit0 solid; bit 1 + (s mod 3) marks a node that
+ * turned solid at the end of step s, kept for the two steps after it, so a
+ * state at step n may also hold the marks of steps n-1 and n-2), then if
  * reaction: m double[N], solid step int32[N] (-1 fluid), removed float[3][N],
- * events lbm_event[n_events]. */
+ * events lbm_event[n_events].  Populations are always saved: in the moment
+ * scheme (lbm_set_scheme) the moments are first unpacked into populations
+ * and the run goes on from those, so a loaded checkpoint continues bit for
+ * bit like the run that saved it. */
 lbm_status lbm_save(lbm_sim* sim, void* blob, size_t cap, size_t* n);
 lbm_status lbm_load(lbm_sim* sim, const void* blob, size_t n);
 
 /* Launch shape of the fused step: tx threads per workgroup (64, 128 or 256)
- * covering tx-2 owned columns, sy owned rows per workgroup (1..4096).
- * The shape changes no result bit. */
+ * covering tx-2 owned columns (tx-4 in the moment scheme), sy owned rows per
+ * workgroup (1..4096).  The shape changes no result bit. */
 lbm_status lbm_set_tile(lbm_sim* sim, int32_t tx, int32_t sy);
 lbm_status lbm_get_tile(const lbm_sim* sim, int32_t* tx, int32_t* sy);
 
@@ -165,10 +170,27 @@ lbm_status lbm_get_tile(const lbm_sim* sim, int32_t* tx, int32_t* sy);
  * traffic, so this costs no time and keeps FP32 rounding to the storage). */
 lbm_status lbm_set_arith(lbm_sim* sim, int32_t bits);
 
+/* State representation between steps (section "LB models": BGK relaxation
+ * with relaxation time tau).  At tau = 1 a collision relaxes every
+ * population fully onto the equilibrium of its component, so the
+ * post-collision state of a node is fixed by (rho_s, v_s) of each component:
+ * LBM_SCHEME_MOMENTS stores those six numbers per node instead of eighteen
+ * populations and rebuilds the populations arriving at a node from the
+ * equilibria of its upstream neighbours (bounce-back: the node's own
+ * equilibrium on the opposite link).  This moves 48 instead of 144 bytes of
+ * flow state per fluid node and step; the results agree with the population
+ * scheme to FP32 rounding.  LBM_SCHEME_AUTO (default) takes moments when
+ * tau == 1 and populations otherwise; LBM_SCHEME_MOMENTS with tau != 1 is
+ * LBM_EINVAL.  The first step after init or load reads populations.
+ * Observers and checkpoints work in both schemes. */
+enum { LBM_SCHEME_AUTO = 0, LBM_SCHEME_POPULATIONS = 1, LBM_SCHEME_MOMENTS = 2 };
+lbm_status lbm_set_scheme(lbm_sim* sim, int32_t scheme);
+
 /* Time the launch shapes (steps_per_candidate steps each, on a saved copy of
  * the state, which is restored), keep the fastest and report it.  When the
  * environment variable LBM_AUTOTUNE_CACHE names a file, a cached choice for
- * the same (GPU architecture, nx x ny, solute/reaction switches, arithmetic)
+ * the same (GPU architecture, nx x ny, solute/reaction switches, arithmetic,
+ * scheme)
  * is used without timing, and new choices are appended to it as JSON lines
  * {"key": ..., "tx": ..., "sy": ..., "ms": ...}. */
 lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_candidate, int32_t* tx, int32_t* sy,
@@ -200,6 +222,10 @@ lbm_status lbm_batch_init(int32_t n, const lbm_params* p, const uint8_t* const* 
 /* Launch shape (tx 64/128/256, sy >= 8); changes no result bit. */
 lbm_status lbm_batch_set_tile(lbm_batch* b, int32_t tx, int32_t sy);
 lbm_status lbm_batch_get_tile(const lbm_batch* b, int32_t* tx, int32_t* sy);
+
+/* As lbm_set_scheme, for every instance; only before the first step (the
+ * tau of the batch decides LBM_SCHEME_AUTO). */
+lbm_status lbm_batch_set_scheme(lbm_batch* b, int32_t scheme);
 
 /* chunk > 0: lbm_batch_step replays a HIP graph of `chunk` captured steps
  * (captured at first use) and launches the remainder directly; 0: direct. */

@@ -40,7 +40,7 @@ namespace {
   } while (0)
 
 constexpr uint64_t kMagic = 0x4C424D5853494D31ull;  // "LBMXSIM1"
-constexpr int kVersion = 1;
+constexpr int kVersion = 2;  // 2: three rotating pending bits in the mask
 
 struct Layout {
   long long N = 0, P = 0, ev_cap = 0;
@@ -110,8 +110,6 @@ lbm_status check_params(const lbm_params* p) {
   return LBM_OK;
 }
 
-unsigned pending_bit(long long n) { return (n & 1) ? 4u : 2u; }  // bit written by step n
-
 }  // namespace
 
 struct lbm_sim {
@@ -123,6 +121,8 @@ struct lbm_sim {
   long long step;  // current state index
   int tx, sy;
   int arith64;     // 1: FP64 arithmetic in the step (storage stays FP32)
+  int scheme;      // LBM_SCHEME_*
+  bool mom;        // f[cur] holds moments of the last step, not populations
   bool poisoned;
   float* f(int i) const { return (float*)(ws + L.f[i]); }
   float* g(int i) const { return L.solute ? (float*)(ws + L.g[i]) : nullptr; }
@@ -151,8 +151,35 @@ void default_tile(const lbm_params& p, int* tx, int* sy) {
   *sy = 16;
 }
 
+bool use_moments(int scheme, const lbm_params& p) {
+  return scheme == LBM_SCHEME_MOMENTS || (scheme == LBM_SCHEME_AUTO && p.tau == 1.0);
+}
+
+// Populations of the current state written over the stored moments (the
+// idle buffer is the scratch), so the state is held as populations again.
+lbm_status materialize(lbm_sim* s) {
+  if (!s->mom) return LBM_OK;
+  const lbm_params& p = s->p;
+  hipError_t e = launch_unpack(s->f(s->cur), s->mask(), p.nx, p.ny, s->L.P,
+                               1u | pending_bit(s->step - 2), s->f(s->cur ^ 1), s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->f(s->cur), s->f(s->cur ^ 1), 18 * s->L.P * sizeof(float),
+                       hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) {
+    s->poisoned = true;
+    return fail(LBM_EDEVICE, "unpack moments: %s", hipGetErrorString(e));
+  }
+  s->mom = false;
+  return LBM_OK;
+}
+
 lbm_status queue_steps(lbm_sim* s, long long n) {
   const lbm_params& p = s->p;
+  const bool moments = use_moments(s->scheme, p);
+  if (n > 0 && !moments && s->mom) {
+    lbm_status st = materialize(s);
+    if (st != LBM_OK) return st;
+  }
   StepArgs a{};
   a.mask = s->mask();
   a.m = s->m();
@@ -164,11 +191,8 @@ lbm_status queue_steps(lbm_sim* s, long long n) {
   a.P = s->L.P;
   a.nx = p.nx;
   a.ny = p.ny;
-  a.tx_owned = s->tx - 2;
   a.sy = s->sy;
-  a.nstrips = (p.nx + a.tx_owned - 1) / a.tx_owned;
   a.nsegs = (p.ny + s->sy - 1) / s->sy;
-  a.remap = (a.nstrips * a.nsegs) >= 8;
   a.solute = s->L.solute;
   a.react = s->L.react;
   a.omega = (float)(1.0 / p.tau);
@@ -182,20 +206,26 @@ lbm_status queue_steps(lbm_sim* s, long long n) {
   a.k_r = p.k_r;
   a.threshold = p.threshold;
   for (long long t = 0; t < n; ++t) {
+    const int kind = !moments ? KIND_POP : (s->mom ? KIND_MM : KIND_PM);
+    a.tx_owned = s->tx - (kind == KIND_MM ? 4 : 2);
+    a.nstrips = (p.nx + a.tx_owned - 1) / a.tx_owned;
+    a.remap = (a.nstrips * a.nsegs) >= 8;
     a.fin = s->f(s->cur);
     a.fout = s->f(s->cur ^ 1);
     a.gin = s->g(s->cur);
     a.gout = s->g(s->cur ^ 1);
     a.step = s->step;
-    a.bit_prev = pending_bit(s->step - 1);
+    a.bit_p1 = pending_bit(s->step - 1);
+    a.bit_p2 = pending_bit(s->step - 2);
     a.bit_cur = pending_bit(s->step);
-    hipError_t e = launch_step(a, s->tx, s->arith64, s->stream);
+    hipError_t e = launch_step(a, s->tx, s->arith64, kind, s->stream);
     if (e != hipSuccess) {
       s->poisoned = true;
       return fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
     }
     s->cur ^= 1;
     s->step += 1;
+    s->mom = kind != KIND_POP;
   }
   return LBM_OK;
 }
@@ -284,6 +314,8 @@ lbm_status lbm_init(const lbm_params* p, const uint8_t* solid, const double* rho
   s->step = 0;
   default_tile(*p, &s->tx, &s->sy);
   s->arith64 = 1;
+  s->scheme = LBM_SCHEME_AUTO;
+  s->mom = false;
   // stage the FP64 inputs in the second population buffer (72 B per node)
   char* stage = (char*)s->f(1);
   hipStream_t hs = s->stream;
@@ -315,9 +347,9 @@ lbm_status lbm_observe(lbm_sim* s, lbm_obs* o) {
   if (st != LBM_OK) return st;
   if (!o) return fail(LBM_EINVAL, "out is NULL");
   const lbm_params& p = s->p;
-  const unsigned bp = pending_bit(s->step - 1);
   hipError_t e = launch_observe(s->f(s->cur), s->g(s->cur), s->mask(), s->m(), s->drop(),
-                                s->sstep(), s->L.N, s->L.P, p.nx, bp, s->L.solute, s->L.react,
+                                s->sstep(), p.nx, p.ny, s->L.P, pending_bit(s->step - 1),
+                                pending_bit(s->step - 2), s->mom, s->L.solute, s->L.react,
                                 s->L.nblocks, s->partial(), s->out(), p.x_in, p.x_out, p.y0, p.W,
                                 s->stream);
   if (e != hipSuccess) { s->poisoned = true; return fail(LBM_EDEVICE, "observe launch: %s", hipGetErrorString(e)); }
@@ -368,9 +400,10 @@ lbm_status lbm_fields(lbm_sim* s, uint32_t mask, double* host) {
   // the next step overwrites every fluid slot of it before reading it
   double* stage = (double*)s->f(s->cur ^ 1);
   hipError_t e = launch_fields(s->f(s->cur), s->g(s->cur), s->mask(), s->m(), p.nx, p.ny, s->L.P,
-                               pending_bit(s->step - 1), s->L.solute, s->L.react, (float)p.G,
-                               (float)p.G_ads[0], (float)p.G_ads[1], (float)p.accel[0],
-                               (float)p.accel[1], stage, s->stream);
+                               pending_bit(s->step - 1), pending_bit(s->step - 2), s->mom,
+                               s->L.solute, s->L.react, (float)p.G, (float)p.G_ads[0],
+                               (float)p.G_ads[1], (float)p.accel[0], (float)p.accel[1], stage,
+                               s->stream);
   int k = 0;
   for (int b = 0; b < 7 && e == hipSuccess; ++b) {
     if (!(mask & (1u << b))) continue;
@@ -411,6 +444,10 @@ lbm_status lbm_save(lbm_sim* s, void* blob, size_t cap, size_t* n) {
   *n = need;
   if (!blob) return LBM_OK;
   if (cap < need) return fail(LBM_EINVAL, "blob too small: %zu < %zu", cap, need);
+  // a checkpoint holds populations: moments are unpacked first, and the run
+  // continues from those FP32 populations, so a resumed run is bit-identical
+  lbm_status mst = materialize(s);
+  if (mst != LBM_OK) return mst;
   char* b = (char*)blob;
   const long long N = s->L.N, P = s->L.P;
   const int32_t hdr32[4] = {s->p.nx, s->p.ny, (s->L.solute ? 1 : 0) | (s->L.react ? 2 : 0), kVersion};
@@ -460,9 +497,9 @@ lbm_status lbm_load(lbm_sim* s, const void* blob, size_t n) {
   if (n != blob_size(s, nev)) return fail(LBM_EINVAL, "checkpoint size mismatch");
   b += 40;
   const long long N = s->L.N, P = s->L.P;
-  // the mask must hold only bit0 and the pending bit of the last step taken
+  // the mask may hold only bit0 and the pending bits of the last two steps
   const char* mb = b + 18 * N * 4 + (s->L.solute ? 5 * N * 4 : 0);
-  const unsigned allowed = 1u | pending_bit(step - 1);
+  const unsigned allowed = 1u | pending_bit(step - 1) | pending_bit(step - 2);
   for (long long i = 0; i < N; ++i)
     if ((unsigned)(uint8_t)mb[i] & ~allowed) return fail(LBM_EINVAL, "bad mask byte at node %lld", i);
   lbm_status st;
@@ -488,7 +525,18 @@ lbm_status lbm_load(lbm_sim* s, const void* blob, size_t n) {
   HIPCHECK(hipStreamSynchronize(s->stream));
   s->cur = 0;
   s->step = step;
+  s->mom = false;
   s->poisoned = false;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_scheme(lbm_sim* s, int32_t scheme) {
+  if (!s) return fail(LBM_EINVAL, "handle is NULL");
+  if (scheme != LBM_SCHEME_AUTO && scheme != LBM_SCHEME_POPULATIONS && scheme != LBM_SCHEME_MOMENTS)
+    return fail(LBM_EINVAL, "unknown scheme %d", scheme);
+  if (scheme == LBM_SCHEME_MOMENTS && s->p.tau != 1.0)
+    return fail(LBM_EINVAL, "the moment scheme needs tau = 1");
+  s->scheme = scheme;
   return LBM_OK;
 }
 
@@ -514,10 +562,12 @@ lbm_status lbm_get_tile(const lbm_sim* s, int32_t* tx, int32_t* sy) {
   return LBM_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Autotune cache: a JSON-lines file named by LBM_AUTOTUNE_CACHE, one object
-// per line {"key": "<arch>:<nx>x<ny>:<flags>:<arith>", "tx": .., "sy": .., "ms": ..}.
+// per line {"key": "<arch>:<nx>x<ny>:<flags>:<arith>:<scheme>", "tx": .., "sy": .., "ms": ..}.
 std::string tune_key(const lbm_sim* s) {
   hipDeviceProp_t prop{};
   int dev = 0;
@@ -528,8 +578,9 @@ std::string tune_key(const lbm_sim* s) {
       if (*c == ':' || *c == '"' || *c == ' ') *c = '_';
   }
   char buf[160];
-  snprintf(buf, sizeof buf, "%s:%dx%d:%d:%d", arch, s->p.nx, s->p.ny,
-           (s->L.solute ? 1 : 0) | (s->L.react ? 2 : 0), s->arith64 ? 64 : 32);
+  snprintf(buf, sizeof buf, "%s:%dx%d:%d:%d:%s", arch, s->p.nx, s->p.ny,
+           (s->L.solute ? 1 : 0) | (s->L.react ? 2 : 0), s->arith64 ? 64 : 32,
+           use_moments(s->scheme, s->p) ? "mom" : "pop");
   return buf;
 }
 
@@ -563,6 +614,8 @@ void tune_store(const std::string& key, int tx, int sy, double ms) {
 }
 
 }  // namespace
+
+extern "C" {
 
 lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_out, double* best_ms) {
   lbm_status st = guard(s);
@@ -653,6 +706,8 @@ struct lbm_batch {
   int max_blocks;
   long long step;
   int tx, sy, arith64;
+  int scheme;                 // LBM_SCHEME_*
+  bool mom;                   // instance buffers hold moments of the last step
   bool solute, react, poisoned;
   int graph_chunk;
   hipGraphExec_t graph;
@@ -668,9 +723,17 @@ struct BatchLayout {
   int max_tiles, max_blocks;
 };
 
+// Columns a workgroup of tx threads owns: the moment step's stencil reaches
+// two columns out, the population step's one; a batch that uses the moment
+// scheme runs its first (population-in) step on the same tiling.
+int owned_cols(int tx, bool moments) { return tx - (moments ? 4 : 2); }
+
 int tiles_for(const lbm_params& p, int tx, int sy) {
-  return ((p.nx + tx - 3) / (tx - 2)) * ((p.ny + sy - 1) / sy);
+  const int own = owned_cols(tx, true);
+  return ((p.nx + own - 1) / own) * ((p.ny + sy - 1) / sy);
 }
+
+bool batch_moments(const lbm_batch* b) { return use_moments(b->scheme, b->p[0]); }
 
 lbm_status batch_layout(int n, const lbm_params* p, int nslots, BatchLayout* B) {
   if (n < 1 || !p) return fail(LBM_EINVAL, "batch needs n >= 1 parameter records");
@@ -735,7 +798,7 @@ StepArgs instance_args(const lbm_batch* b, int i, int parity) {
   a.P = L.P;
   a.nx = p.nx;
   a.ny = p.ny;
-  a.tx_owned = b->tx - 2;
+  a.tx_owned = owned_cols(b->tx, batch_moments(b));
   a.sy = b->sy;
   a.nstrips = (p.nx + a.tx_owned - 1) / a.tx_owned;
   a.nsegs = (p.ny + b->sy - 1) / b->sy;
@@ -771,8 +834,9 @@ lbm_status batch_configure(lbm_batch* b) {
     b->h_insts[2 * i + 1] = instance_args(b, i, 1);
   }
   std::vector<int4> order;
+  const int own = owned_cols(b->tx, batch_moments(b));
   for (int i = 0; i < b->n; ++i) {
-    const int ns = (b->p[i].nx + b->tx - 3) / (b->tx - 2), nq = (b->p[i].ny + b->sy - 1) / b->sy;
+    const int ns = (b->p[i].nx + own - 1) / own, nq = (b->p[i].ny + b->sy - 1) / b->sy;
     for (int s = 0; s < ns; ++s)
       for (int q = 0; q < nq; ++q) order.push_back(make_int4(i, s, q, 0));
   }
@@ -809,19 +873,26 @@ lbm_status batch_reset(lbm_batch* b) {
   HIPCHECK(hipMemsetAsync(b->d_step, 0, sizeof(long long), b->stream));
   HIPCHECK(hipStreamSynchronize(b->stream));
   b->step = 0;
+  b->mom = false;
   return LBM_OK;
+}
+
+int batch_kind(const lbm_batch* b) {
+  return !batch_moments(b) ? KIND_POP : (b->mom ? KIND_MM : KIND_PM);
 }
 
 lbm_status batch_launch(lbm_batch* b, long long nsteps) {
   for (long long t = 0; t < nsteps; ++t) {
+    const int kind = batch_kind(b);
     hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, b->tx,
-                                     b->solute, b->react, b->arith64, b->stream);
+                                     b->solute, b->react, b->arith64, kind, b->stream);
     if (e != hipSuccess) {
       b->poisoned = true;
       return fail(LBM_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
     }
+    b->step += 1;
+    b->mom = kind != KIND_POP;
   }
-  b->step += nsteps;
   return LBM_OK;
 }
 
@@ -894,6 +965,8 @@ lbm_status lbm_batch_init(int32_t n, const lbm_params* p, const uint8_t* const* 
   b->tx = 128;
   b->sy = 24;
   b->arith64 = 1;
+  b->scheme = LBM_SCHEME_AUTO;
+  b->mom = false;
   b->solute = solute;
   b->react = p[0].k_r > 0.0;
   b->graph = nullptr;
@@ -903,7 +976,6 @@ lbm_status lbm_batch_init(int32_t n, const lbm_params* p, const uint8_t* const* 
   for (int i = 0; i < n; ++i) {
     const long long N = b->L[i].N;
     char* stg = b->ws + b->stage[i];
-    char* w = b->ws + b->base[i];
     capi[i] = make_int4(p[i].x_in, p[i].x_out, p[i].y0, p[i].W);
 #define BCK(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) { delete b; return fail(LBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); } } while (0)
     BCK(hipMemcpyAsync(stg, rho1[i], N * 8, hipMemcpyHostToDevice, b->stream));
@@ -945,6 +1017,12 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
   if (st != LBM_OK) return st;
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
   long long left = nsteps;
+  // the first step of a moment-scheme run reads populations: launch it
+  // directly, so that the captured chunk holds moment steps only
+  if (left > 0 && batch_kind(b) == KIND_PM) {
+    if ((st = batch_launch(b, 1)) != LBM_OK) return st;
+    left -= 1;
+  }
   if (b->graph_chunk > 0 && left >= b->graph_chunk) {
     if (!b->graph) {
       // capture chunk steps once; the kernels read the step index from the
@@ -956,7 +1034,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
       HIPCHECK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int t = 0; t < b->graph_chunk; ++t) {
         hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, b->tx,
-                                         b->solute, b->react, b->arith64, b->cap_stream);
+                                         b->solute, b->react, b->arith64, batch_kind(b),
+                                         b->cap_stream);
         if (e != hipSuccess) {
           (void)hipStreamEndCapture(b->cap_stream, &g);
           if (g) (void)hipGraphDestroy(g);
@@ -984,8 +1063,8 @@ lbm_status lbm_batch_record_fronts(lbm_batch* b, int32_t slot) {
   lbm_status st = bguard(b);
   if (st != LBM_OK) return st;
   if (slot < 0 || slot >= b->nslots) return fail(LBM_EINVAL, "slot out of range");
-  HIPCHECK(launch_front_batch(b->d_insts, b->d_capi, b->d_step, b->n, slot, b->nslots, b->d_table,
-                              b->stream));
+  HIPCHECK(launch_front_batch(b->d_insts, b->d_capi, b->d_step, b->n, slot, b->nslots, b->mom,
+                              b->d_table, b->stream));
   return LBM_OK;
 }
 
@@ -1006,9 +1085,9 @@ lbm_status lbm_batch_observe(lbm_batch* b, int32_t i, lbm_obs* o) {
   const lbm_params& p = b->p[i];
   const StepArgs& a = b->h_insts[2 * i + (int)(b->step & 1)];
   const Layout& L = b->L[i];
-  const unsigned bp = pending_bit(b->step - 1);
   const int nblocks = (int)std::min<long long>(b->max_blocks, (L.N + 255) / 256);
-  hipError_t e = launch_observe(a.fin, a.gin, a.mask, a.m, a.drop, a.sstep, L.N, L.P, p.nx, bp,
+  hipError_t e = launch_observe(a.fin, a.gin, a.mask, a.m, a.drop, a.sstep, p.nx, p.ny, L.P,
+                                pending_bit(b->step - 1), pending_bit(b->step - 2), b->mom,
                                 L.solute, L.react, nblocks, b->d_partial, b->d_out, p.x_in, p.x_out,
                                 p.y0, p.W, b->stream);
   double h[OBS_OUT];
@@ -1048,9 +1127,10 @@ lbm_status lbm_batch_fields(lbm_batch* b, int32_t i, uint32_t mask, double* host
   const long long N = b->L[i].N;
   double* stage = (double*)a.fout;  // idle buffer: rewritten by the next step before it is read
   hipError_t e = launch_fields(a.fin, a.gin, a.mask, a.m, p.nx, p.ny, b->L[i].P,
-                               pending_bit(b->step - 1), b->L[i].solute, b->L[i].react, (float)p.G,
-                               (float)p.G_ads[0], (float)p.G_ads[1], (float)p.accel[0],
-                               (float)p.accel[1], stage, b->stream);
+                               pending_bit(b->step - 1), pending_bit(b->step - 2), b->mom,
+                               b->L[i].solute, b->L[i].react, (float)p.G, (float)p.G_ads[0],
+                               (float)p.G_ads[1], (float)p.accel[0], (float)p.accel[1], stage,
+                               b->stream);
   int k = 0;
   for (int bit = 0; bit < 7 && e == hipSuccess; ++bit) {
     if (!(mask & (1u << bit))) continue;
@@ -1123,6 +1203,18 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* tx_out, int3
   if (sy_out) *sy_out = bsy;
   if (best_ms) *best_ms = best / steps;
   return LBM_OK;
+}
+
+lbm_status lbm_batch_set_scheme(lbm_batch* b, int32_t scheme) {
+  lbm_status st = bguard(b);
+  if (st != LBM_OK) return st;
+  if (scheme != LBM_SCHEME_AUTO && scheme != LBM_SCHEME_POPULATIONS && scheme != LBM_SCHEME_MOMENTS)
+    return fail(LBM_EINVAL, "unknown scheme %d", scheme);
+  if (scheme == LBM_SCHEME_MOMENTS && b->p[0].tau != 1.0)
+    return fail(LBM_EINVAL, "the moment scheme needs tau = 1");
+  if (b->step != 0) return fail(LBM_EINVAL, "the batch scheme is chosen before the first step");
+  b->scheme = scheme;
+  return batch_configure(b);
 }
 
 lbm_status lbm_batch_get_tile(const lbm_batch* b, int32_t* tx, int32_t* sy) {

@@ -8,34 +8,45 @@
 // Memory layout in HBM (structure of arrays, plane stride P >= nx*ny, P a
 // multiple of 64 so every plane starts 256-byte aligned):
 //   f  float[18][P]  populations, component-major, link order
-//                    (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1)
+//                    (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1);
+//                    in the moment scheme planes 0..5 hold instead the
+//                    post-collision moments rho1, v1x, v1y, rho2, v2x, v2y
 //   g  float[5][P]   solute populations (first five links)
-//   mask uint8[P]    bit0 solid; bit1 / bit2 growth pending, set by the step
-//                    of even / odd parity
+//   mask uint8[P]    bit0 solid; bits 1..3 growth pending (see pending_bit)
 //   m  double[P]     precipitated mass (touched only at wall-adjacent nodes)
 //   sstep int32[P]   state index at which the node turned solid (-1 fluid)
 //   drop float[3][P] populations a node carried when it turned solid
-// f and g are double-buffered (A/B); a step reads one buffer and pushes into
-// the other.
+// f and g are double-buffered (A/B); a step reads one buffer and writes the
+// other.
 //
-// Fused step, one kernel per time step.  A workgroup of TX threads owns
-// TX-2 consecutive columns (one column per thread, plus one halo column on
-// each side) and SY consecutive rows, and marches up its rows.  For every row
-// it loads the node populations (coalesced along x), forms the densities,
-// puts rho1, rho2 and the solid flag of the row into a 4-row LDS ring, and
-// then collides the row below with the cohesion/adhesion stencil read from
-// LDS, applies the reaction, and pushes the post-collision populations to the
-// neighbours (or back into the node's own opposite link at a solid neighbour).
-// Per-node arithmetic does not depend on the launch shape, so every tile shape
-// gives bit-identical results.
+// Population step (any tau), one kernel per time step.  A workgroup of TX
+// threads owns TX-2 consecutive columns (one column per thread, plus one halo
+// column on each side) and SY consecutive rows, and marches up its rows.  For
+// every row it loads the node populations (coalesced along x), forms the
+// densities, puts rho1, rho2 and the solid flag of the row into a 4-row LDS
+// ring, and then collides the row below with the cohesion/adhesion stencil
+// read from LDS, applies the reaction, and pushes the post-collision
+// populations to the neighbours (or back into the node's own opposite link at
+// a solid neighbour).
+//
+// Moment step (tau = 1).  With full relaxation the post-collision populations
+// of a component are its equilibria at (rho_s, v_s), so a node stores those
+// three numbers per component (24 bytes instead of 72) and the next step
+// rebuilds the populations that arrive at x by evaluating the equilibrium of
+// each upstream neighbour (halfway bounce-back: the node's own moments with
+// the velocity reversed when the upstream node is solid).  A workgroup then
+// owns TX-4 columns: the gathered densities feed the force stencil, which
+// reaches two columns and two rows out.  Per-node arithmetic is independent
+// of the launch shape in both steps, so every tile shape gives bit-identical
+// results.
 //
 // Growth timing.  In the step n -> n+1 a node whose precipitate exceeds the
-// threshold still streams as fluid (the step uses the mask of state n); it is
-// marked pending with the bit of parity n.  In the next step every thread
-// reads bit0 | pending(n) as the solid flag, and the owner of the node books
-// its populations into `drop` and folds the pending bit into bit0.  A node
-// being marked in the current step is read as fluid by its neighbours, so
-// concurrent workgroups never disagree on the mask.
+// threshold still streams as fluid (the step uses the solid set of state n);
+// it is marked with pending_bit(n).  Step n+1 reads it as solid and books the
+// populations it carried into `drop`; step n+2 folds the mark into bit0.  A
+// node being marked in the current step is read as fluid by its neighbours,
+// so concurrent workgroups never disagree on the solid sets of states n-1
+// and n, which the moment step needs both of.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -68,18 +79,168 @@ __device__ __forceinline__ void lds_barrier(int TX) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Shan-Chen interaction forces plus the body force at a fluid node (section
+// "LB models": cohesion between the two components and adhesion to the solid,
+// each a weight-normalised sum over the eight neighbours).  n1, n2: the
+// neighbours' densities (zero at solid nodes); sf: their solid flags (0/1);
+// index = link, 1..8 = E, N, W, S, NE, NW, SW, SE (index 0 unused).
+template <typename R>
+__device__ __forceinline__ void sc_forces(const StepArgs& a, const R* n1, const R* n2,
+                                          const float* sf, R rho1, R rho2, R& F1x, R& F1y,
+                                          R& F2x, R& F2y) {
+  const R WA = R(1) / R(9), WD = R(1) / R(36);
+  const R c2x = WA * (n2[1] - n2[3]) + WD * ((n2[5] - n2[6]) + (n2[8] - n2[7]));
+  const R c2y = WA * (n2[2] - n2[4]) + WD * ((n2[5] + n2[6]) - (n2[8] + n2[7]));
+  const R c1x = WA * (n1[1] - n1[3]) + WD * ((n1[5] - n1[6]) + (n1[8] - n1[7]));
+  const R c1y = WA * (n1[2] - n1[4]) + WD * ((n1[5] + n1[6]) - (n1[8] + n1[7]));
+  const R csx = WA * R(sf[1] - sf[3]) + WD * R((sf[5] - sf[6]) + (sf[8] - sf[7]));
+  const R csy = WA * R(sf[2] - sf[4]) + WD * R((sf[5] + sf[6]) - (sf[8] + sf[7]));
+  const R G = (R)a.G, Ga1 = (R)a.Gads1, Ga2 = (R)a.Gads2, ax = (R)a.ax, ay = (R)a.ay;
+  F1x = -G * rho1 * c2x - Ga1 * rho1 * csx + rho1 * ax;
+  F1y = -G * rho1 * c2y - Ga1 * rho1 * csy + rho1 * ay;
+  F2x = -G * rho2 * c1x - Ga2 * rho2 * csx + rho2 * ax;
+  F2y = -G * rho2 * c1y - Ga2 * rho2 * csy + rho2 * ay;
+}
+
+// Equilibrium velocities of the two components (common velocity shifted by
+// tau F_s / rho_s) and the physical velocity (j + F/2) / rho that advects the
+// solute.
+template <typename R>
+__device__ __forceinline__ void sc_velocities(R tau, R rho1, R rho2, R j1x, R j1y, R j2x, R j2y,
+                                              R F1x, R F1y, R F2x, R F2y, R& v1x, R& v1y,
+                                              R& v2x, R& v2y, R& ux, R& uy) {
+  const R rt = rho1 + rho2;
+  const R irt = R(1) / rt;
+  const R upx = (j1x + j2x) * irt, upy = (j1y + j2y) * irt;
+  v1x = upx; v1y = upy; v2x = upx; v2y = upy;
+  if (rho1 > R(0)) { const R s = tau / rho1; v1x += s * F1x; v1y += s * F1y; }
+  if (rho2 > R(0)) { const R s = tau / rho2; v2x += s * F2x; v2y += s * F2y; }
+  ux = (j1x + j2x + R(0.5) * (F1x + F2x)) * irt;
+  uy = (j1y + j2y + R(0.5) * (F1y + F2y)) * irt;
+}
+
+// Solute collision (D2Q5 BGK advected by u), first-order precipitation at a
+// node with ns > 0 solid axis neighbours (rate k_r ns phi, phi the wetting
+// fraction), threshold test, and push of the solute populations (bounce-back
+// at solid axis neighbours).  sf: solid flags of the axis neighbours 1..4.
+template <bool REACT, typename R>
+__device__ __forceinline__ void solute_step(const StepArgs& a, const float* g, R ux, R uy,
+                                            R rho1, R rho2, const float* sf, double m_cur,
+                                            unsigned P, unsigned idx, unsigned iE, unsigned iN,
+                                            unsigned iW, unsigned iS, int xc, int y, bool& ev,
+                                            int& evx, int& evy) {
+  const R W5A = R(1) / R(6);
+  const R C = (((R)g[0] + (R)g[1]) + ((R)g[2] + (R)g[3])) + (R)g[4];
+  const R og = (R)a.omega_g;
+  R gs[5];
+  gs[1] = (R)g[1] + og * (W5A * C * (R(1) + R(3) * ux) - (R)g[1]);
+  gs[2] = (R)g[2] + og * (W5A * C * (R(1) + R(3) * uy) - (R)g[2]);
+  gs[3] = (R)g[3] + og * (W5A * C * (R(1) - R(3) * ux) - (R)g[3]);
+  gs[4] = (R)g[4] + og * (W5A * C * (R(1) - R(3) * uy) - (R)g[4]);
+  gs[0] = C - ((gs[1] + gs[2]) + (gs[3] + gs[4]));
+  if (REACT) {
+    const int ns = (int)sf[1] + (int)sf[2] + (int)sf[3] + (int)sf[4];
+    if (ns > 0) {
+      const double phi = (double)rho1 / ((double)rho1 + (double)rho2);
+      const double rr = a.k_r * (double)ns * phi;
+      const double mm = m_cur + rr * (double)C;
+      a.m[idx] = mm;
+      const R keep = (R)(1.0 - rr);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) gs[q] *= keep;
+      if (mm > a.threshold) {
+        a.mask[idx] = (uint8_t)a.bit_cur;
+        a.sstep[idx] = (int32_t)(a.step + 1);
+        ev = true;
+        evx = xc;
+        evy = y;
+      }
+    }
+  }
+  float* __restrict__ go = a.gout;
+  go[idx] = (float)gs[0];
+  if (sf[1] != 0.0f) go[3 * P + idx] = (float)gs[1]; else go[1 * P + iE] = (float)gs[1];
+  if (sf[2] != 0.0f) go[4 * P + idx] = (float)gs[2]; else go[2 * P + iN] = (float)gs[2];
+  if (sf[3] != 0.0f) go[1 * P + idx] = (float)gs[3]; else go[3 * P + iW] = (float)gs[3];
+  if (sf[4] != 0.0f) go[2 * P + idx] = (float)gs[4]; else go[4 * P + iS] = (float)gs[4];
+}
+
+// One lane per wavefront reserves event-log slots for every lane that marked
+// a node in this row, with a single atomic.
+__device__ __forceinline__ void log_events(const StepArgs& a, bool ev, int evx, int evy) {
+  const int lane = __lane_id();
+  const unsigned long long bal = __ballot(ev);
+  if (bal) {
+    const int leader = __ffsll((unsigned long long)bal) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(a.ev_count, (unsigned long long)__popcll(bal));
+    base = __shfl(base, leader);
+    if (ev) {
+      const unsigned long long e = base + __popcll(bal & ((1ull << lane) - 1ull));
+      if ((long long)e < a.ev_cap) {
+        a.ev[e].x = evx;
+        a.ev[e].y = evy;
+        a.ev[e].step = a.step + 1;
+      }
+    }
+  }
+}
+
+// Incoming populations of a node in state n rebuilt from stored moments
+// (moment scheme, tau = 1).  r, vx, vy: the node's own post-collision moments
+// (index 0) and those of the upstream node x - e_i of link i (index i); up[i]:
+// that upstream node was fluid in state n-1.  A link whose upstream node was
+// solid carries the node's own equilibrium on the opposite link (halfway
+// bounce-back), i.e. the same expression with the node's velocity reversed.
+// f[0] is the node's own rest equilibrium.
+template <typename R>
+__device__ __forceinline__ void gather_links(const float* r, const float* vx, const float* vy,
+                                             const bool* up, R* f) {
+  const R WA = R(1) / R(9), WD = R(1) / R(36), W0 = R(4) / R(9);
+  const R r0 = (R)r[0], x0 = (R)vx[0], y0 = (R)vy[0];
+  const R uu0 = x0 * x0 + y0 * y0;
+  f[0] = feq<R>(W0, r0, R(0), uu0);
+#define GL(i, w, EU)                                                  \
+  do {                                                                \
+    const R rr = up[i] ? (R)r[i] : r0;                                \
+    const R ux = up[i] ? (R)vx[i] : -x0;                              \
+    const R uy = up[i] ? (R)vy[i] : -y0;                              \
+    const R uu = up[i] ? ux * ux + uy * uy : uu0;                     \
+    f[i] = feq<R>(w, rr, EU, uu);                                     \
+  } while (0)
+  GL(1, WA, ux);
+  GL(2, WA, uy);
+  GL(3, WA, -ux);
+  GL(4, WA, -uy);
+  GL(5, WD, ux + uy);
+  GL(6, WD, -ux + uy);
+  GL(7, WD, -ux - uy);
+  GL(8, WD, ux - uy);
+#undef GL
+}
+
+// Density and momentum of nine populations (the summation order of the
+// population step).
+template <typename R>
+__device__ __forceinline__ void moments9(const R* f, R& rho, R& jx, R& jy) {
+  rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+}
+
 // R is the arithmetic type (float or double); populations are stored as FP32.
 //
-// Per workgroup, iteration k handles row r = ys - 1 + k: its populations,
-// precipitate (owned rows) and the mask byte of row k+1 are requested
-// together (the mask of row k arrived one iteration earlier), so each
-// iteration waits on one memory round trip.  The densities of row k go to
-// the LDS ring; after an LDS-only barrier row k-1 is collided and pushed.
+// Population step.  Per workgroup, iteration k handles row r = ys - 1 + k: its
+// populations, precipitate (owned rows) and the mask byte of row k+1 are
+// requested together (the mask of row k arrived one iteration earlier), so
+// each iteration waits on one memory round trip.  The densities of row k go
+// to the LDS ring; after an LDS-only barrier row k-1 is collided and pushed.
 // Offsets are 32-bit (the host guarantees 23 planes fit below 2^31).  The
 // register budget is held to three waves per SIMD: a row iteration costs one
 // memory round trip plus ~1 us of VALU work per wave, so resident waves are
-// what hides the memory latency.
-template <bool SOLUTE, bool REACT, typename R>
+// what hides the memory latency.  OUTM (tau = 1 only): store the moments
+// (rho_s, v_s) of the collided node instead of pushing populations.
+template <bool SOLUTE, bool REACT, typename R, bool OUTM>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
   const int TX = blockDim.x;
   R* s_r1 = (R*)lds_raw;                 // [4][TX] density of component 1 (0 at solid)
@@ -101,9 +262,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
   const int ys = seg * a.sy;
   const int ye = min(ys + a.sy, ny);
   const int nrows = ye - ys + 2;
-  const unsigned solid_bits = 1u | a.bit_prev;
-  const int lane = __lane_id();
-  const R WA = R(1) / R(9), WD = R(1) / R(36), W5A = R(1) / R(6);
+  const unsigned SPREV = 1u | a.bit_p2;    // solid in state n-1
+  const unsigned SCUR = SPREV | a.bit_p1;  // solid in state n
   const float* __restrict__ fin = a.fin;
   const float* __restrict__ gin = a.gin;
   const uint8_t* __restrict__ maskp = a.mask;
@@ -126,7 +286,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
     const bool owned_row = k >= 1 && k <= nrows - 2;
     b_nxt = mask_ahead;
     if (active) {
-      if (!(b_nxt & 1u)) {
+      if (!(b_nxt & SPREV)) {
 #pragma unroll
         for (int q = 0; q < 18; ++q) fn[q] = fin[q * P + idn];
         if (SOLUTE && owner && owned_row) {
@@ -143,7 +303,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
     __builtin_amdgcn_s_waitcnt(VMCNT0);
     R r1 = R(0), r2 = R(0);
     float sv = 1.0f;
-    if (active && !(b_nxt & solid_bits)) {
+    if (active && !(b_nxt & SCUR)) {
       r1 = sum9<R>(fn);
       r2 = sum9<R>(fn + 9);
       sv = 0.0f;
@@ -163,69 +323,64 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
       const int yu = y == ny - 1 ? 0 : y + 1;
       const unsigned idx = (unsigned)y * (unsigned)nx + (unsigned)xc;
       const int sb = ((k - 2) & 3) * TX, sm = ((k - 1) & 3) * TX, sa = (k & 3) * TX;
-      const R* A1 = s_r1;
-      const R* A2 = s_r2;
-      const float* AS = s_s;
-      if (AS[sm + t] != 0.0f) {
-        if (REACT && (b_cur & a.bit_prev)) {
-          // turned solid at the end of the previous step: book its populations
-          a.drop[idx] = (float)sum9<R>(f);
-          a.drop[P + idx] = (float)sum9<R>(f + 9);
-          a.drop[2 * P + idx] =
-              SOLUTE ? (float)((((R)g[0] + (R)g[1]) + ((R)g[2] + (R)g[3])) + (R)g[4]) : 0.0f;
-          a.mask[idx] = 1;
+      if (s_s[sm + t] != 0.0f) {
+        if (REACT) {
+          if (b_cur & a.bit_p1) {
+            // turned solid at the end of the previous step: book its populations
+            a.drop[idx] = (float)sum9<R>(f);
+            a.drop[P + idx] = (float)sum9<R>(f + 9);
+            a.drop[2 * P + idx] =
+                SOLUTE ? (float)((((R)g[0] + (R)g[1]) + ((R)g[2] + (R)g[3])) + (R)g[4]) : 0.0f;
+          } else if (b_cur & a.bit_p2) {
+            a.mask[idx] = 1;  // booked one step ago: fold the mark into bit0
+          }
         }
       } else {
-        const R rho1 = A1[sm + t], rho2 = A2[sm + t];
-        const float sE = AS[sm + t + 1], sN = AS[sa + t], sW = AS[sm + t - 1], sS = AS[sb + t];
-        const float sNE = AS[sa + t + 1], sNW = AS[sa + t - 1], sSW = AS[sb + t - 1], sSE = AS[sb + t + 1];
-        // sum_i w_i v(x+e_i) e_i of the other component and of the solid mask
-        const R c2x = WA * (A2[sm + t + 1] - A2[sm + t - 1]) +
-                      WD * ((A2[sa + t + 1] - A2[sa + t - 1]) + (A2[sb + t + 1] - A2[sb + t - 1]));
-        const R c2y = WA * (A2[sa + t] - A2[sb + t]) +
-                      WD * ((A2[sa + t + 1] + A2[sa + t - 1]) - (A2[sb + t + 1] + A2[sb + t - 1]));
-        const R c1x = WA * (A1[sm + t + 1] - A1[sm + t - 1]) +
-                      WD * ((A1[sa + t + 1] - A1[sa + t - 1]) + (A1[sb + t + 1] - A1[sb + t - 1]));
-        const R c1y = WA * (A1[sa + t] - A1[sb + t]) +
-                      WD * ((A1[sa + t + 1] + A1[sa + t - 1]) - (A1[sb + t + 1] + A1[sb + t - 1]));
-        const R csx = WA * R(sE - sW) + WD * R((sNE - sNW) + (sSE - sSW));
-        const R csy = WA * R(sN - sS) + WD * R((sNE + sNW) - (sSE + sSW));
-
-        const R G = (R)a.G, Ga1 = (R)a.Gads1, Ga2 = (R)a.Gads2, ax = (R)a.ax, ay = (R)a.ay;
-        const R F1x = -G * rho1 * c2x - Ga1 * rho1 * csx + rho1 * ax;
-        const R F1y = -G * rho1 * c2y - Ga1 * rho1 * csy + rho1 * ay;
-        const R F2x = -G * rho2 * c1x - Ga2 * rho2 * csx + rho2 * ax;
-        const R F2y = -G * rho2 * c1y - Ga2 * rho2 * csy + rho2 * ay;
-
+        const R rho1 = s_r1[sm + t], rho2 = s_r2[sm + t];
+        // neighbours in link order 1..8 = E, N, W, S, NE, NW, SW, SE
+        const int no[9] = {sm + t, sm + t + 1, sa + t, sm + t - 1, sb + t,
+                           sa + t + 1, sa + t - 1, sb + t - 1, sb + t + 1};
+        R n1[9], n2[9];
+        float sf[9];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          n1[i] = s_r1[no[i]];
+          n2[i] = s_r2[no[i]];
+          sf[i] = s_s[no[i]];
+        }
+        R F1x, F1y, F2x, F2y;
+        sc_forces<R>(a, n1, n2, sf, rho1, rho2, F1x, F1y, F2x, F2y);
         const R j1x = ((R)f[1] - (R)f[3]) + ((R)f[5] - (R)f[6]) + ((R)f[8] - (R)f[7]);
         const R j1y = ((R)f[2] - (R)f[4]) + ((R)f[5] + (R)f[6]) - ((R)f[7] + (R)f[8]);
         const R j2x = ((R)f[10] - (R)f[12]) + ((R)f[14] - (R)f[15]) + ((R)f[17] - (R)f[16]);
         const R j2y = ((R)f[11] - (R)f[13]) + ((R)f[14] + (R)f[15]) - ((R)f[16] + (R)f[17]);
+        R v1x, v1y, v2x, v2y, ux, uy;
+        sc_velocities<R>((R)a.tau, rho1, rho2, j1x, j1y, j2x, j2y, F1x, F1y, F2x, F2y, v1x, v1y,
+                         v2x, v2y, ux, uy);
 
-        const R rt = rho1 + rho2;
-        const R irt = R(1) / rt;
-        const R upx = (j1x + j2x) * irt, upy = (j1y + j2y) * irt;
-        const R tau = (R)a.tau;
-        R v1x = upx, v1y = upy, v2x = upx, v2y = upy;
-        if (rho1 > R(0)) { const R s = tau / rho1; v1x += s * F1x; v1y += s * F1y; }
-        if (rho2 > R(0)) { const R s = tau / rho2; v2x += s * F2x; v2y += s * F2y; }
-        const R ux = (j1x + j2x + R(0.5) * (F1x + F2x)) * irt;
-        const R uy = (j1y + j2y + R(0.5) * (F1y + F2y)) * irt;
-
-        // target offsets of the eight neighbours
+        // target offsets of the four axis neighbours (and the diagonals)
         const unsigned iE = (unsigned)y * nx + xr, iW = (unsigned)y * nx + xl;
         const unsigned iN = (unsigned)yu * nx + xc, iS = (unsigned)yd * nx + xc;
-        const unsigned iNE = (unsigned)yu * nx + xr, iNW = (unsigned)yu * nx + xl;
-        const unsigned iSW = (unsigned)yd * nx + xl, iSE = (unsigned)yd * nx + xr;
         float* __restrict__ fo = a.fout;
-        const R om = (R)a.omega;
-        // collide one component and push each moving population as soon as it
-        // is formed (halfway bounce-back into the node's own opposite link at
-        // a solid neighbour); the rest population closes the mass balance
-        // exactly (the moving-link weights are not exact binary fractions)
-        auto collide_push = [&](const float* fc, unsigned base, R rho, R vx, R vy) {
-          const R uu = vx * vx + vy * vy;
-          R sum = R(0);
+        if (OUTM) {
+          fo[idx] = (float)rho1;
+          fo[P + idx] = (float)v1x;
+          fo[2 * P + idx] = (float)v1y;
+          fo[3 * P + idx] = (float)rho2;
+          fo[4 * P + idx] = (float)v2x;
+          fo[5 * P + idx] = (float)v2y;
+        } else {
+          const unsigned iNE = (unsigned)yu * nx + xr, iNW = (unsigned)yu * nx + xl;
+          const unsigned iSW = (unsigned)yd * nx + xl, iSE = (unsigned)yd * nx + xr;
+          const R om = (R)a.omega;
+          // collide one component and push each moving population as soon as
+          // it is formed (halfway bounce-back into the node's own opposite
+          // link at a solid neighbour); the rest population closes the mass
+          // balance exactly (the moving-link weights are not exact binary
+          // fractions)
+          auto collide_push = [&](const float* fc, unsigned base, R rho, R vx, R vy) {
+            const R uu = vx * vx + vy * vy;
+            R sum = R(0);
 #define CP(i, opp, w, eu, bs, tgt)                                          \
   do {                                                                      \
     const R fi = (R)fc[i];                                                  \
@@ -234,75 +389,27 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
     if (bs != 0.0f) fo[(base + (opp)) * P + idx] = (float)v;                \
     else fo[(base + (i)) * P + (tgt)] = (float)v;                           \
   } while (0)
-          CP(1, 3, WA, vx, sE, iE);
-          CP(2, 4, WA, vy, sN, iN);
-          CP(3, 1, WA, -vx, sW, iW);
-          CP(4, 2, WA, -vy, sS, iS);
-          CP(5, 7, WD, vx + vy, sNE, iNE);
-          CP(6, 8, WD, -vx + vy, sNW, iNW);
-          CP(7, 5, WD, -vx - vy, sSW, iSW);
-          CP(8, 6, WD, vx - vy, sSE, iSE);
+            const R WA = R(1) / R(9), WD = R(1) / R(36);
+            CP(1, 3, WA, vx, sf[1], iE);
+            CP(2, 4, WA, vy, sf[2], iN);
+            CP(3, 1, WA, -vx, sf[3], iW);
+            CP(4, 2, WA, -vy, sf[4], iS);
+            CP(5, 7, WD, vx + vy, sf[5], iNE);
+            CP(6, 8, WD, -vx + vy, sf[6], iNW);
+            CP(7, 5, WD, -vx - vy, sf[7], iSW);
+            CP(8, 6, WD, vx - vy, sf[8], iSE);
 #undef CP
-          fo[base * P + idx] = (float)(rho - sum);
-        };
-        collide_push(f, 0u, rho1, v1x, v1y);
-        collide_push(f + 9, 9u, rho2, v2x, v2y);
-
-        if (SOLUTE) {
-          const R C = (((R)g[0] + (R)g[1]) + ((R)g[2] + (R)g[3])) + (R)g[4];
-          const R og = (R)a.omega_g;
-          R gs[5];
-          gs[1] = (R)g[1] + og * (W5A * C * (R(1) + R(3) * ux) - (R)g[1]);
-          gs[2] = (R)g[2] + og * (W5A * C * (R(1) + R(3) * uy) - (R)g[2]);
-          gs[3] = (R)g[3] + og * (W5A * C * (R(1) - R(3) * ux) - (R)g[3]);
-          gs[4] = (R)g[4] + og * (W5A * C * (R(1) - R(3) * uy) - (R)g[4]);
-          gs[0] = C - ((gs[1] + gs[2]) + (gs[3] + gs[4]));
-          if (REACT) {
-            const int ns = (int)sE + (int)sN + (int)sW + (int)sS;
-            if (ns > 0) {
-              const double phi = (double)rho1 / ((double)rho1 + (double)rho2);
-              const double rr = a.k_r * (double)ns * phi;
-              const double mm = m_cur + rr * (double)C;
-              a.m[idx] = mm;
-              const R keep = (R)(1.0 - rr);
-#pragma unroll
-              for (int q = 0; q < 5; ++q) gs[q] *= keep;
-              if (mm > a.threshold) {
-                a.mask[idx] = (uint8_t)a.bit_cur;
-                a.sstep[idx] = (int32_t)(a.step + 1);
-                ev = true;
-                evx = xc;
-                evy = y;
-              }
-            }
-          }
-          float* __restrict__ go = a.gout;
-          go[idx] = (float)gs[0];
-          if (sE != 0.0f) go[3 * P + idx] = (float)gs[1]; else go[1 * P + iE] = (float)gs[1];
-          if (sN != 0.0f) go[4 * P + idx] = (float)gs[2]; else go[2 * P + iN] = (float)gs[2];
-          if (sW != 0.0f) go[1 * P + idx] = (float)gs[3]; else go[3 * P + iW] = (float)gs[3];
-          if (sS != 0.0f) go[2 * P + idx] = (float)gs[4]; else go[4 * P + iS] = (float)gs[4];
+            fo[base * P + idx] = (float)(rho - sum);
+          };
+          collide_push(f, 0u, rho1, v1x, v1y);
+          collide_push(f + 9, 9u, rho2, v2x, v2y);
         }
+        if (SOLUTE)
+          solute_step<REACT, R>(a, g, ux, uy, rho1, rho2, sf, m_cur, P, idx, iE, iN, iW, iS, xc, y,
+                                ev, evx, evy);
       }
     }
-    if (REACT) {
-      // one atomic per wavefront reserves the event-log slots of its lanes
-      const unsigned long long bal = __ballot(ev);
-      if (bal) {
-        const int leader = __ffsll((unsigned long long)bal) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(a.ev_count, (unsigned long long)__popcll(bal));
-        base = __shfl(base, leader);
-        if (ev) {
-          const unsigned long long e = base + __popcll(bal & ((1ull << lane) - 1ull));
-          if ((long long)e < a.ev_cap) {
-            a.ev[e].x = evx;
-            a.ev[e].y = evy;
-            a.ev[e].step = a.step + 1;
-          }
-        }
-      }
-    }
+    if (REACT) log_events(a, ev, evx, evy);
     // rotate: row k becomes the row to collide next iteration
 #pragma unroll
     for (int q = 0; q < 18; ++q) f[q] = fn[q];
@@ -315,6 +422,196 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
   }
 }
 
+// Moment step (tau = 1).  Thread t holds column x0 - 2 + t.  Iteration k:
+//   A  rows ys-2+k: stored moments (fluid nodes of state n-1) and mask bytes
+//      into LDS rings; the solute populations and, at wall-adjacent nodes, the
+//      precipitate of row k-2 are requested in the same round trip;
+//   B  row k-1: incoming populations gathered from the 3x3 moments, giving
+//      rho_s and j_s; the densities go to an LDS ring (zero at solids);
+//   C  row k-2: forces from the density ring, new moments stored, solute
+//      collided, reacted and pushed, growth marks and bookings.
+// LDS: moments float[3][6][TX], densities R[3][2][TX], mask bytes u8[8][TX].
+template <bool SOLUTE, bool REACT, typename R>
+__device__ __forceinline__ void mom_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
+  const int TX = blockDim.x;
+  float* sM = (float*)lds_raw;
+  R* sR = (R*)(sM + 18 * TX);
+  uint8_t* sK = (uint8_t*)(sR + 6 * TX);
+
+  const int t = threadIdx.x;
+  const int nx = a.nx, ny = a.ny;
+  const unsigned P = (unsigned)a.P;
+  const int x0 = strip * a.tx_owned;
+  const int nown = min(a.tx_owned, nx - x0);
+  const bool active = t <= nown + 3;
+  const bool gatherer = t >= 1 && t <= nown + 2;
+  const bool owner = t >= 2 && t <= nown + 1;
+  int xc = x0 - 2 + t;
+  if (xc < 0) xc += nx;
+  if (xc >= nx) xc -= nx;
+  const int xl = xc == 0 ? nx - 1 : xc - 1;
+  const int xr = xc == nx - 1 ? 0 : xc + 1;
+  const int ys = seg * a.sy;
+  const int ye = min(ys + a.sy, ny);
+  const int nrows = ye - ys + 4;
+  const unsigned SPREV = 1u | a.bit_p2;    // solid in state n-1
+  const unsigned SCUR = SPREV | a.bit_p1;  // solid in state n
+  const float* __restrict__ Min = a.fin;
+  const float* __restrict__ gin = a.gin;
+  const uint8_t* __restrict__ maskp = a.mask;
+
+  auto row_y = [&](int k) {
+    int yr = ys - 2 + k;
+    if (yr < 0) yr += ny;
+    if (yr >= ny) yr -= ny;
+    return yr;
+  };
+
+  unsigned mk_ahead = active ? (unsigned)maskp[(unsigned)row_y(0) * (unsigned)nx + (unsigned)xc] : 1u;
+  unsigned mk0 = 1u, mk1 = 1u, mk2 = 1u;  // own mask bytes of rows k, k-1, k-2
+  R rC1 = R(0), rC2 = R(0), jC1x = R(0), jC1y = R(0), jC2x = R(0), jC2y = R(0);
+  int c0 = 0, c1 = 1, c2 = 2;  // ring slots of rows k, k-2 (= k+1 mod 3), k-1
+
+  for (int k = 0; k < nrows; ++k) {
+    // ---- requests: moments of row k, mask of row k+1, solute of row k-2 ---
+    mk0 = mk_ahead;
+    float mv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (active) {
+      const unsigned ida = (unsigned)row_y(k) * (unsigned)nx + (unsigned)xc;
+      if (!(mk0 & SPREV)) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) mv[q] = Min[q * P + ida];
+      }
+      if (k + 1 < nrows) mk_ahead = maskp[(unsigned)row_y(k + 1) * (unsigned)nx + (unsigned)xc];
+    } else {
+      mk0 = 1u;
+    }
+    const bool crow = k >= 4 && owner;
+    const int yC = ys + k - 4;
+    const unsigned idxC = (unsigned)(crow ? yC : 0) * (unsigned)nx + (unsigned)xc;
+    float gv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    double mC = 0.0;
+    if (crow) {
+      if (SOLUTE && !(mk2 & SPREV)) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) gv[q] = gin[q * P + idxC];
+      }
+      if (REACT && !(mk2 & SCUR)) {
+        const int kb = ((k - 3) & 7) * TX, km = ((k - 2) & 7) * TX, ka = ((k - 1) & 7) * TX;
+        const bool wall = ((sK[km + t + 1] | sK[ka + t] | sK[km + t - 1] | sK[kb + t]) & SCUR) != 0;
+        if (wall) mC = a.m[idxC];
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sM[(c0 * 6 + q) * TX + t] = mv[q];
+    sK[(k & 7) * TX + t] = (uint8_t)mk0;
+    lds_barrier(TX);
+
+    // ---- B: gather row k-1 -------------------------------------------------
+    R rN1 = R(0), rN2 = R(0), jN1x = R(0), jN1y = R(0), jN2x = R(0), jN2y = R(0);
+    if (k >= 2 && gatherer) {
+      if (!(mk1 & SPREV)) {
+        const int kB = ((k - 2) & 7) * TX, kM = ((k - 1) & 7) * TX, kA = (k & 7) * TX;
+        // upstream node x - e_i of link i: 1 W, 2 S, 3 E, 4 N, 5 SW, 6 SE, 7 NE, 8 NW
+        const int mc[9] = {t, t - 1, t, t + 1, t, t - 1, t + 1, t + 1, t - 1};
+        const int ms[9] = {c2, c2, c1, c2, c0, c1, c1, c0, c0};
+        const int ks[9] = {kM, kM, kB, kM, kA, kB, kB, kA, kA};
+        bool up[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) up[i] = !(sK[ks[i] + mc[i]] & SPREV);
+        float r[9], vx[9], vy[9];
+        R fl[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          r[i] = sM[(ms[i] * 6 + 0) * TX + mc[i]];
+          vx[i] = sM[(ms[i] * 6 + 1) * TX + mc[i]];
+          vy[i] = sM[(ms[i] * 6 + 2) * TX + mc[i]];
+        }
+        gather_links<R>(r, vx, vy, up, fl);
+        moments9<R>(fl, rN1, jN1x, jN1y);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          r[i] = sM[(ms[i] * 6 + 3) * TX + mc[i]];
+          vx[i] = sM[(ms[i] * 6 + 4) * TX + mc[i]];
+          vy[i] = sM[(ms[i] * 6 + 5) * TX + mc[i]];
+        }
+        gather_links<R>(r, vx, vy, up, fl);
+        moments9<R>(fl, rN2, jN2x, jN2y);
+      }
+      const bool sol = (mk1 & SCUR) != 0;
+      sR[(c2 * 2 + 0) * TX + t] = sol ? R(0) : rN1;
+      sR[(c2 * 2 + 1) * TX + t] = sol ? R(0) : rN2;
+    }
+    lds_barrier(TX);
+
+    // ---- C: collide row k-2 ------------------------------------------------
+    bool ev = false;
+    int evx = 0, evy = 0;
+    if (crow) {
+      const int y = yC;
+      const unsigned idx = idxC;
+      if (mk2 & SCUR) {
+        if (REACT) {
+          if (mk2 & a.bit_p1) {
+            // turned solid at the end of the previous step: book what it carried
+            a.drop[idx] = (float)rC1;
+            a.drop[P + idx] = (float)rC2;
+            a.drop[2 * P + idx] =
+                SOLUTE ? (float)((((R)gv[0] + (R)gv[1]) + ((R)gv[2] + (R)gv[3])) + (R)gv[4]) : 0.0f;
+          } else if (mk2 & a.bit_p2) {
+            a.mask[idx] = 1;  // booked one step ago: fold the mark into bit0
+          }
+        }
+      } else {
+        const int kb = ((k - 3) & 7) * TX, km = ((k - 2) & 7) * TX, ka = ((k - 1) & 7) * TX;
+        // neighbours x + e_i in link order 1..8 = E, N, W, S, NE, NW, SW, SE
+        const int nc[9] = {t, t + 1, t, t - 1, t, t + 1, t - 1, t - 1, t + 1};
+        const int nsl[9] = {c1, c1, c2, c1, c0, c2, c2, c0, c0};
+        const int nk[9] = {km, km, ka, km, kb, ka, ka, kb, kb};
+        R n1[9], n2[9];
+        float sf[9];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          n1[i] = sR[(nsl[i] * 2 + 0) * TX + nc[i]];
+          n2[i] = sR[(nsl[i] * 2 + 1) * TX + nc[i]];
+          sf[i] = (sK[nk[i] + nc[i]] & SCUR) ? 1.0f : 0.0f;
+        }
+        R F1x, F1y, F2x, F2y;
+        sc_forces<R>(a, n1, n2, sf, rC1, rC2, F1x, F1y, F2x, F2y);
+        R v1x, v1y, v2x, v2y, ux, uy;
+        sc_velocities<R>((R)a.tau, rC1, rC2, jC1x, jC1y, jC2x, jC2y, F1x, F1y, F2x, F2y, v1x, v1y,
+                         v2x, v2y, ux, uy);
+        float* __restrict__ fo = a.fout;
+        fo[idx] = (float)rC1;
+        fo[P + idx] = (float)v1x;
+        fo[2 * P + idx] = (float)v1y;
+        fo[3 * P + idx] = (float)rC2;
+        fo[4 * P + idx] = (float)v2x;
+        fo[5 * P + idx] = (float)v2y;
+        if (SOLUTE) {
+          const int yd = y == 0 ? ny - 1 : y - 1;
+          const int yu = y == ny - 1 ? 0 : y + 1;
+          const unsigned iE = (unsigned)y * nx + xr, iW = (unsigned)y * nx + xl;
+          const unsigned iN = (unsigned)yu * nx + xc, iS = (unsigned)yd * nx + xc;
+          solute_step<REACT, R>(a, gv, ux, uy, rC1, rC2, sf, mC, P, idx, iE, iN, iW, iS, xc, y, ev,
+                                evx, evy);
+        }
+      }
+    }
+    if (REACT) log_events(a, ev, evx, evy);
+    // rotate the register pipeline and the ring slots
+    rC1 = rN1; rC2 = rN2;
+    jC1x = jN1x; jC1y = jN1y; jC2x = jN2x; jC2y = jN2y;
+    mk2 = mk1;
+    mk1 = mk0;
+    const int cz = c0;
+    c0 = c1;
+    c1 = c2;
+    c2 = cz;
+  }
+}
+
 // XCD-aware order: the hardware hands block b to XCD b mod 8, so XCD x
 // receives q + (x < r) of T blocks (q = T / 8, r = T mod 8).  Give each XCD a
 // contiguous run of tiles, so vertically adjacent segments of a strip share
@@ -324,14 +621,22 @@ __host__ __device__ inline int xcd_tile(int b, int T) {
   return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
-template <bool SOLUTE, bool REACT, typename R>
+template <bool SOLUTE, bool REACT, typename R, int KIND>
+__device__ __forceinline__ void run_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
+  if (KIND == KIND_MM)
+    mom_tile<SOLUTE, REACT, R>(a, strip, seg, lds_raw);
+  else
+    step_tile<SOLUTE, REACT, R, KIND == KIND_PM>(a, strip, seg, lds_raw);
+}
+
+template <bool SOLUTE, bool REACT, typename R, int KIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_step(const StepArgs a) {
   extern __shared__ char lds_raw[];
   const int T = a.nstrips * a.nsegs;
   const int tile = a.remap ? xcd_tile(blockIdx.x, T) : (int)blockIdx.x;
   const int strip = tile / a.nsegs;
-  step_tile<SOLUTE, REACT, R>(a, strip, tile - strip * a.nsegs, lds_raw);
+  run_tile<SOLUTE, REACT, R, KIND>(a, strip, tile - strip * a.nsegs, lds_raw);
 }
 
 // Batched step: one launch advances every instance of a batch by one step.
@@ -339,7 +644,7 @@ k_step(const StepArgs a) {
 // list per XCD); the instance's arguments for the current parity come from
 // device memory, and the step index from the device counter, so a sequence of
 // launches can be captured once in a graph and replayed.
-template <bool SOLUTE, bool REACT, typename R>
+template <bool SOLUTE, bool REACT, typename R, int KIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_step_batch(const StepArgs* __restrict__ insts, const int4* __restrict__ tiles,
              const long long* __restrict__ stepc) {
@@ -348,9 +653,10 @@ k_step_batch(const StepArgs* __restrict__ insts, const int4* __restrict__ tiles,
   const int4 e = tiles[blockIdx.x];
   StepArgs a = insts[2 * e.x + (int)(step & 1)];
   a.step = step;
-  a.bit_prev = ((step - 1) & 1) ? 4u : 2u;
-  a.bit_cur = (step & 1) ? 4u : 2u;
-  step_tile<SOLUTE, REACT, R>(a, e.y, e.z, lds_raw);
+  a.bit_p1 = pending_bit(step - 1);
+  a.bit_p2 = pending_bit(step - 2);
+  a.bit_cur = pending_bit(step);
+  run_tile<SOLUTE, REACT, R, KIND>(a, e.y, e.z, lds_raw);
 }
 
 // Advances the device step counter (a vector atomic, one lane).
@@ -392,17 +698,89 @@ __global__ void k_init(const double* __restrict__ rho1, const double* __restrict
   }
 }
 
+// ---- observers -------------------------------------------------------------
+// Node densities and momenta of state n, from stored populations or, in the
+// moment scheme, gathered from the stored moments of the node and its
+// upstream neighbours (the same arithmetic as the moment step, in FP64).
+struct PopSrc {
+  const float* __restrict__ f;
+  long long P;
+  __device__ void rho(long long i, int, int, double& r1, double& r2) const {
+    double a = 0, b = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      a += (double)f[q * P + i];
+      b += (double)f[(9 + q) * P + i];
+    }
+    r1 = a;
+    r2 = b;
+  }
+  __device__ void full(long long i, int, int, double* o) const {
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    double r1 = 0, r2 = 0, j1x = 0, j1y = 0, j2x = 0, j2y = 0;
+    for (int q = 0; q < 9; ++q) {
+      const double a = f[q * P + i], b = f[(9 + q) * P + i];
+      r1 += a; r2 += b;
+      j1x += a * ex[q]; j1y += a * ey[q];
+      j2x += b * ex[q]; j2y += b * ey[q];
+    }
+    o[0] = r1; o[1] = r2; o[2] = j1x; o[3] = j1y; o[4] = j2x; o[5] = j2y;
+  }
+};
+
+struct MomSrc {
+  const float* __restrict__ M;
+  const uint8_t* __restrict__ mask;
+  long long P;
+  int nx, ny;
+  unsigned sprev;  // solid bits of state n-1
+  __device__ void links(int x, int y, int comp, double* fl) const {
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    float r[9], vx[9], vy[9];
+    bool up[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      int xs = x - ex[q], ysrc = y - ey[q];
+      xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+      ysrc = ysrc < 0 ? ysrc + ny : (ysrc >= ny ? ysrc - ny : ysrc);
+      const long long k = (long long)ysrc * nx + xs;
+      up[q] = !(mask[k] & sprev);
+      r[q] = M[(3 * comp) * P + k];
+      vx[q] = M[(3 * comp + 1) * P + k];
+      vy[q] = M[(3 * comp + 2) * P + k];
+    }
+    gather_links<double>(r, vx, vy, up, fl);
+  }
+  __device__ void full(long long, int x, int y, double* o) const {
+    double fl[9];
+    links(x, y, 0, fl);
+    moments9<double>(fl, o[0], o[2], o[3]);
+    links(x, y, 1, fl);
+    moments9<double>(fl, o[1], o[4], o[5]);
+  }
+  __device__ void rho(long long i, int x, int y, double& r1, double& r2) const {
+    double o[6];
+    full(i, x, y, o);
+    r1 = o[0];
+    r2 = o[1];
+  }
+};
+
 // Observe, pass 1: per-block FP64 partial sums.  Slots:
 // 0 mass1, 1 mass2, 2 solute, 3 precipitate, 4 removed1, 5 removed2,
 // 6 removed solute, 7 solid count, 8 non-finite count.
-__global__ void __launch_bounds__(256) k_obs_partial(const float* __restrict__ f,
-                                                     const float* __restrict__ g,
+template <typename Src>
+__global__ void __launch_bounds__(256) k_obs_partial(Src src, const float* __restrict__ g,
                                                      const uint8_t* __restrict__ mask,
                                                      const double* __restrict__ m,
-                                                     const float* __restrict__ drop, long long N,
-                                                     long long P, unsigned bit_prev, int solute,
-                                                     int react, double* __restrict__ partial) {
+                                                     const float* __restrict__ drop, int nx,
+                                                     long long N, long long P, unsigned p1,
+                                                     unsigned p2, int solute, int react,
+                                                     double* __restrict__ partial) {
   __shared__ double red[OBS_SLOTS][256];
+  const unsigned sprev = 1u | p2, scur = sprev | p1;
   double acc[OBS_SLOTS];
 #pragma unroll
   for (int j = 0; j < OBS_SLOTS; ++j) acc[j] = 0.0;
@@ -410,20 +788,16 @@ __global__ void __launch_bounds__(256) k_obs_partial(const float* __restrict__ f
        i += (long long)gridDim.x * blockDim.x) {
     const unsigned b = mask[i];
     double s1 = 0, s2 = 0, sc = 0;
-    if (!(b & 1u)) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        s1 += (double)f[q * P + i];
-        s2 += (double)f[(9 + q) * P + i];
-      }
+    if (!(b & sprev)) {
+      src.rho(i, (int)(i % nx), (int)(i / nx), s1, s2);
       if (solute) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) sc += (double)g[q * P + i];
       }
     }
-    if (b & (1u | bit_prev)) {
+    if (b & scur) {
       acc[7] += 1.0;
-      if (b & bit_prev) {  // turned solid at the end of the last step, not yet booked
+      if (b & p1) {  // turned solid at the end of the last step, not yet booked
         acc[4] += s1;
         acc[5] += s2;
         acc[6] += sc;
@@ -463,29 +837,16 @@ __global__ void k_obs_final(const double* __restrict__ partial, int nblocks, dou
   out[j] = s;
 }
 
-__device__ __forceinline__ void node_rho(const float* __restrict__ f, long long P, long long i,
-                                         double* r1, double* r2) {
-  double a = 0, b = 0;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    a += (double)f[q * P + i];
-    b += (double)f[(9 + q) * P + i];
-  }
-  *r1 = a;
-  *r2 = b;
-}
-
 // Capillary observables computed by one workgroup of 256 threads: centreline
 // front, largest grown width and first closure.  out: [0] z, [1] delta_e,
-// [2] closure step (-1 if none).
-__device__ void capillary_obs(const float* __restrict__ f, const uint8_t* __restrict__ mask,
-                              const int32_t* __restrict__ sstep, int nx, long long P,
-                              unsigned bit_prev, int x_in, int x_out, int y0, int W, int react,
-                              double* __restrict__ out) {
+// [2] closure step (-1 if none).  sb: solid bits of state n.
+template <typename Src>
+__device__ void capillary_obs(const Src& src, const uint8_t* __restrict__ mask,
+                              const int32_t* __restrict__ sstep, int nx, unsigned sb, int x_in,
+                              int x_out, int y0, int W, int react, double* __restrict__ out) {
   __shared__ int s_min[256];
   __shared__ double s_de[256];
   __shared__ long long s_cl[256];
-  const unsigned sb = 1u | bit_prev;
   const int nr = (W % 2 == 0) ? 2 : 1;
   const int row0 = (W % 2 == 0) ? (y0 + W / 2 - 1) : (y0 + (W - 1) / 2);
   int best = x_out;  // first x where the scan stops
@@ -498,14 +859,14 @@ __device__ void capillary_obs(const float* __restrict__ f, const uint8_t* __rest
     for (int r = 0; r < nr; ++r) {
       const long long i = (long long)(row0 + r) * nx + x;
       if (mask[i] & sb) blocked = true;
-      else { double a, b; node_rho(f, P, i, &a, &b); phi += a / (a + b); }
+      else { double a, b; src.rho(i, x, row0 + r, a, b); phi += a / (a + b); }
     }
     phi /= nr;
     if (x + 1 < x_out) {
       for (int r = 0; r < nr; ++r) {
         const long long i = (long long)(row0 + r) * nx + x + 1;
         if (mask[i] & sb) nblocked = true;
-        else { double a, b; node_rho(f, P, i, &a, &b); phin += a / (a + b); }
+        else { double a, b; src.rho(i, x + 1, row0 + r, a, b); phin += a / (a + b); }
       }
       phin /= nr;
     }
@@ -553,7 +914,7 @@ __device__ void capillary_obs(const float* __restrict__ f, const uint8_t* __rest
       for (int r = 0; r < nr; ++r) {
         const long long i = (long long)(row0 + r) * nx + x;
         if (mask[i] & sb) blocked = true;
-        else { double a, b; node_rho(f, P, i, &a, &b); phi += a / (a + b); }
+        else { double a, b; src.rho(i, x, row0 + r, a, b); phi += a / (a + b); }
       }
       phi /= nr;
       if (blocked) z = (double)(x - x_in);
@@ -561,7 +922,7 @@ __device__ void capillary_obs(const float* __restrict__ f, const uint8_t* __rest
       else {
         for (int r = 0; r < nr; ++r) {
           const long long i = (long long)(row0 + r) * nx + x + 1;
-          double a, b; node_rho(f, P, i, &a, &b); phin += a / (a + b);
+          double a, b; src.rho(i, x + 1, row0 + r, a, b); phin += a / (a + b);
         }
         phin /= nr;
         z = (double)x + (phi - 0.5) / (phi - phin) - x_in;
@@ -573,13 +934,13 @@ __device__ void capillary_obs(const float* __restrict__ f, const uint8_t* __rest
   }
 }
 
-__global__ void __launch_bounds__(256) k_obs_capillary(const float* __restrict__ f,
-                                                       const uint8_t* __restrict__ mask,
+template <typename Src>
+__global__ void __launch_bounds__(256) k_obs_capillary(Src src, const uint8_t* __restrict__ mask,
                                                        const int32_t* __restrict__ sstep,
-                                                       int nx, long long P, unsigned bit_prev,
-                                                       int x_in, int x_out, int y0, int W,
-                                                       int react, double* __restrict__ out) {
-  capillary_obs(f, mask, sstep, nx, P, bit_prev, x_in, x_out, y0, W, react, out);
+                                                       int nx, unsigned sb, int x_in, int x_out,
+                                                       int y0, int W, int react,
+                                                       double* __restrict__ out) {
+  capillary_obs(src, mask, sstep, nx, sb, x_in, x_out, y0, W, react, out);
 }
 
 // Front of every instance of a batch (workgroup i -> instance i) into column
@@ -587,7 +948,7 @@ __global__ void __launch_bounds__(256) k_obs_capillary(const float* __restrict__
 __global__ void __launch_bounds__(256) k_front_batch(const StepArgs* __restrict__ insts,
                                                      const int4* __restrict__ capi,
                                                      const long long* __restrict__ stepc,
-                                                     int slot, int nslots,
+                                                     int slot, int nslots, int mom,
                                                      double* __restrict__ table) {
   __shared__ double res[3];
   const long long step = *stepc;
@@ -598,19 +959,26 @@ __global__ void __launch_bounds__(256) k_front_batch(const StepArgs* __restrict_
     if (threadIdx.x == 0) table[(long long)i * nslots + slot] = __builtin_nan("");
     return;
   }
-  capillary_obs(a.fin, a.mask, a.sstep, a.nx, a.P, ((step - 1) & 1) ? 4u : 2u, c.x, c.y, c.z,
-                c.w, a.react, res);
+  const unsigned p1 = pending_bit(step - 1), p2 = pending_bit(step - 2);
+  const unsigned sb = 1u | p1 | p2;
+  if (mom) {
+    const MomSrc src{a.fin, a.mask, a.P, a.nx, a.ny, 1u | p2};
+    capillary_obs(src, a.mask, a.sstep, a.nx, sb, c.x, c.y, c.z, c.w, a.react, res);
+  } else {
+    const PopSrc src{a.fin, a.P};
+    capillary_obs(src, a.mask, a.sstep, a.nx, sb, c.x, c.y, c.z, c.w, a.react, res);
+  }
   if (threadIdx.x == 0) table[(long long)i * nslots + slot] = res[0];
 }
 
 // Macroscopic fields of the current state as FP64 planes:
 // 0 rho1, 1 rho2, 2 ux, 3 uy, 4 conc, 5 precipitate, 6 solid.
-__global__ void k_fields(const float* __restrict__ f, const float* __restrict__ g,
-                         const uint8_t* __restrict__ mask, const double* __restrict__ m, int nx,
-                         int ny, long long P, unsigned bit_prev, int solute, int react, float G,
-                         float Gads1, float Gads2, float ax, float ay, double* __restrict__ out) {
+template <typename Src>
+__global__ void k_fields(Src src, const float* __restrict__ g, const uint8_t* __restrict__ mask,
+                         const double* __restrict__ m, int nx, int ny, long long P, unsigned sb,
+                         int solute, int react, float G, float Gads1, float Gads2, float ax,
+                         float ay, double* __restrict__ out) {
   const long long N = (long long)nx * ny;
-  const unsigned sb = 1u | bit_prev;
   const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
@@ -620,13 +988,10 @@ __global__ void k_fields(const float* __restrict__ f, const float* __restrict__ 
     const bool s = (mask[i] & sb) != 0;
     double r1 = 0, r2 = 0, ux = 0, uy = 0, c = 0;
     if (!s) {
-      double j1x = 0, j1y = 0, j2x = 0, j2y = 0;
-      for (int q = 0; q < 9; ++q) {
-        const double a = f[q * P + i], b = f[(9 + q) * P + i];
-        r1 += a; r2 += b;
-        j1x += a * ex[q]; j1y += a * ey[q];
-        j2x += b * ex[q]; j2y += b * ey[q];
-      }
+      double o[6];
+      src.full(i, x, y, o);
+      r1 = o[0];
+      r2 = o[1];
       double c1x = 0, c1y = 0, c2x = 0, c2y = 0, sx = 0, sy = 0;
       for (int q = 1; q < 9; ++q) {
         int xn = x + ex[q], yn = y + ey[q];
@@ -635,7 +1000,7 @@ __global__ void k_fields(const float* __restrict__ f, const float* __restrict__ 
         const long long k = (long long)yn * nx + xn;
         if (mask[k] & sb) { sx += w[q] * ex[q]; sy += w[q] * ey[q]; continue; }
         double a, b;
-        node_rho(f, P, k, &a, &b);
+        src.rho(k, xn, yn, a, b);
         c1x += w[q] * a * ex[q]; c1y += w[q] * a * ey[q];
         c2x += w[q] * b * ex[q]; c2y += w[q] * b * ey[q];
       }
@@ -643,8 +1008,8 @@ __global__ void k_fields(const float* __restrict__ f, const float* __restrict__ 
       const double F1y = -G * r1 * c2y - Gads1 * r1 * sy + r1 * ay;
       const double F2x = -G * r2 * c1x - Gads2 * r2 * sx + r2 * ax;
       const double F2y = -G * r2 * c1y - Gads2 * r2 * sy + r2 * ay;
-      ux = (j1x + j2x + 0.5 * (F1x + F2x)) / (r1 + r2);
-      uy = (j1y + j2y + 0.5 * (F1y + F2y)) / (r1 + r2);
+      ux = (o[2] + o[4] + 0.5 * (F1x + F2x)) / (r1 + r2);
+      uy = (o[3] + o[5] + 0.5 * (F1y + F2y)) / (r1 + r2);
       if (solute)
         for (int q = 0; q < 5; ++q) c += g[q * P + i];
     }
@@ -658,90 +1023,150 @@ __global__ void k_fields(const float* __restrict__ f, const float* __restrict__ 
   }
 }
 
+// Populations of state n rebuilt from the stored moments (zero at nodes that
+// were solid in state n-1, which carry none).
+__global__ void k_unpack(MomSrc src, float* __restrict__ fout) {
+  const long long N = (long long)src.nx * src.ny;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % src.nx), y = (int)(i / src.nx);
+    const bool fluid = !(src.mask[i] & src.sprev);
+    for (int comp = 0; comp < 2; ++comp) {
+      double fl[9];
+      if (fluid) src.links(x, y, comp, fl);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) fout[(9 * comp + q) * src.P + i] = fluid ? (float)fl[q] : 0.0f;
+    }
+  }
+}
+
 // ---- launchers ------------------------------------------------------------
-hipError_t launch_step(const StepArgs& a, int tx, int arith64, hipStream_t st) {
+size_t step_lds_bytes(int kind, int tx, int arith64) {
+  const size_t r = arith64 ? sizeof(double) : sizeof(float);
+  if (kind == KIND_MM) return (size_t)tx * (18 * sizeof(float) + 6 * r + 8);
+  return (size_t)4 * tx * (2 * r + sizeof(float));
+}
+
+template <typename R, int KIND>
+void launch_step_t(const StepArgs& a, int T, int tx, size_t lds, hipStream_t st) {
+  if (a.solute && a.react)
+    hipLaunchKernelGGL((k_step<true, true, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+  else if (a.solute)
+    hipLaunchKernelGGL((k_step<true, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_step<false, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+}
+
+hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, hipStream_t st) {
   const int T = a.nstrips * a.nsegs;
-  const size_t lds = (size_t)4 * tx * (2 * (arith64 ? sizeof(double) : sizeof(float)) + sizeof(float));
+  const size_t lds = step_lds_bytes(kind, tx, arith64);
   if (arith64) {
-    if (a.solute && a.react)
-      hipLaunchKernelGGL((k_step<true, true, double>), dim3(T), dim3(tx), lds, st, a);
-    else if (a.solute)
-      hipLaunchKernelGGL((k_step<true, false, double>), dim3(T), dim3(tx), lds, st, a);
-    else
-      hipLaunchKernelGGL((k_step<false, false, double>), dim3(T), dim3(tx), lds, st, a);
+    if (kind == KIND_MM) launch_step_t<double, KIND_MM>(a, T, tx, lds, st);
+    else if (kind == KIND_PM) launch_step_t<double, KIND_PM>(a, T, tx, lds, st);
+    else launch_step_t<double, KIND_POP>(a, T, tx, lds, st);
   } else {
-    if (a.solute && a.react)
-      hipLaunchKernelGGL((k_step<true, true, float>), dim3(T), dim3(tx), lds, st, a);
-    else if (a.solute)
-      hipLaunchKernelGGL((k_step<true, false, float>), dim3(T), dim3(tx), lds, st, a);
-    else
-      hipLaunchKernelGGL((k_step<false, false, float>), dim3(T), dim3(tx), lds, st, a);
+    if (kind == KIND_MM) launch_step_t<float, KIND_MM>(a, T, tx, lds, st);
+    else if (kind == KIND_PM) launch_step_t<float, KIND_PM>(a, T, tx, lds, st);
+    else launch_step_t<float, KIND_POP>(a, T, tx, lds, st);
   }
   return hipGetLastError();
 }
 
+template <typename R, int KIND>
+void launch_batch_t(const StepArgs* insts, const int4* tiles, int ntiles, const long long* stepc,
+                    int tx, int solute, int react, size_t lds, hipStream_t st) {
+  if (solute && react)
+    hipLaunchKernelGGL((k_step_batch<true, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+  else if (solute)
+    hipLaunchKernelGGL((k_step_batch<true, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+  else
+    hipLaunchKernelGGL((k_step_batch<false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+}
+
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
                              const long long* stepc, int tx, int solute, int react, int arith64,
-                             hipStream_t st) {
-  const size_t lds = (size_t)4 * tx * (2 * (arith64 ? sizeof(double) : sizeof(float)) + sizeof(float));
+                             int kind, hipStream_t st) {
+  const size_t lds = step_lds_bytes(kind, tx, arith64);
   if (arith64) {
-    if (solute && react)
-      hipLaunchKernelGGL((k_step_batch<true, true, double>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
-    else if (solute)
-      hipLaunchKernelGGL((k_step_batch<true, false, double>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
-    else
-      hipLaunchKernelGGL((k_step_batch<false, false, double>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    if (kind == KIND_MM) launch_batch_t<double, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
+    else if (kind == KIND_PM) launch_batch_t<double, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
+    else launch_batch_t<double, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
   } else {
-    if (solute && react)
-      hipLaunchKernelGGL((k_step_batch<true, true, float>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
-    else if (solute)
-      hipLaunchKernelGGL((k_step_batch<true, false, float>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
-    else
-      hipLaunchKernelGGL((k_step_batch<false, false, float>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    if (kind == KIND_MM) launch_batch_t<float, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
+    else if (kind == KIND_PM) launch_batch_t<float, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
+    else launch_batch_t<float, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
   }
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, (long long*)stepc);
   return hipGetLastError();
 }
 
 hipError_t launch_front_batch(const StepArgs* insts, const int4* capi, const long long* stepc,
-                              int n, int slot, int nslots, double* table, hipStream_t st) {
-  hipLaunchKernelGGL(k_front_batch, dim3(n), dim3(256), 0, st, insts, capi, stepc, slot, nslots, table);
+                              int n, int slot, int nslots, int mom, double* table, hipStream_t st) {
+  hipLaunchKernelGGL(k_front_batch, dim3(n), dim3(256), 0, st, insts, capi, stepc, slot, nslots,
+                     mom, table);
   return hipGetLastError();
 }
 
 int host_xcd_tile(int b, int T) { return xcd_tile(b, T); }
 
+static int grid_for(long long N) { return (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192); }
+
 hipError_t launch_init(const double* r1, const double* r2, const double* c, const uint8_t* mask,
                        float* f, float* g, double* m, int32_t* sstep, float* drop, long long N,
                        long long P, int solute, int react, hipStream_t st) {
-  const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
-  hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, st, r1, r2, c, mask, f, g, m, sstep,
+  hipLaunchKernelGGL(k_init, dim3(grid_for(N)), dim3(256), 0, st, r1, r2, c, mask, f, g, m, sstep,
                      drop, N, P, solute, react);
   return hipGetLastError();
 }
 
-hipError_t launch_observe(const float* f, const float* g, const uint8_t* mask, const double* m,
-                          const float* drop, const int32_t* sstep, long long N, long long P,
-                          int nx, unsigned bit_prev, int solute, int react, int nblocks,
-                          double* partial, double* out, int x_in, int x_out, int y0, int W,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_obs_partial, dim3(nblocks), dim3(256), 0, st, f, g, mask, m, drop, N, P,
-                     bit_prev, solute, react, partial);
+hipError_t launch_unpack(const float* M, const uint8_t* mask, int nx, int ny, long long P,
+                         unsigned sprev, float* fout, hipStream_t st) {
+  const MomSrc src{M, mask, P, nx, ny, sprev};
+  hipLaunchKernelGGL(k_unpack, dim3(grid_for((long long)nx * ny)), dim3(256), 0, st, src, fout);
+  return hipGetLastError();
+}
+
+template <typename Src>
+void observe_t(const Src& src, const float* g, const uint8_t* mask, const double* m,
+               const float* drop, const int32_t* sstep, int nx, int ny, long long P, unsigned p1,
+               unsigned p2, int solute, int react, int nblocks, double* partial, double* out,
+               int x_in, int x_out, int y0, int W, hipStream_t st) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_obs_partial<Src>, dim3(nblocks), dim3(256), 0, st, src, g, mask, m, drop,
+                     nx, N, P, p1, p2, solute, react, partial);
   hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(64), 0, st, partial, nblocks, out);
   if (W > 0)
-    hipLaunchKernelGGL(k_obs_capillary, dim3(1), dim3(256), 0, st, f, mask, sstep, nx, P,
-                       bit_prev, x_in, x_out, y0, W, react, out + OBS_SLOTS);
+    hipLaunchKernelGGL(k_obs_capillary<Src>, dim3(1), dim3(256), 0, st, src, mask, sstep, nx,
+                       1u | p1 | p2, x_in, x_out, y0, W, react, out + OBS_SLOTS);
+}
+
+hipError_t launch_observe(const float* f, const float* g, const uint8_t* mask, const double* m,
+                          const float* drop, const int32_t* sstep, int nx, int ny, long long P,
+                          unsigned p1, unsigned p2, int mom, int solute, int react, int nblocks,
+                          double* partial, double* out, int x_in, int x_out, int y0, int W,
+                          hipStream_t st) {
+  if (mom)
+    observe_t(MomSrc{f, mask, P, nx, ny, 1u | p2}, g, mask, m, drop, sstep, nx, ny, P, p1, p2,
+              solute, react, nblocks, partial, out, x_in, x_out, y0, W, st);
+  else
+    observe_t(PopSrc{f, P}, g, mask, m, drop, sstep, nx, ny, P, p1, p2, solute, react, nblocks,
+              partial, out, x_in, x_out, y0, W, st);
   return hipGetLastError();
 }
 
 hipError_t launch_fields(const float* f, const float* g, const uint8_t* mask, const double* m,
-                         int nx, int ny, long long P, unsigned bit_prev, int solute, int react,
-                         float G, float Gads1, float Gads2, float ax, float ay, double* out,
-                         hipStream_t st) {
-  const long long N = (long long)nx * ny;
-  const int blocks = (int)((N + 255) / 256 < 8192 ? (N + 255) / 256 : 8192);
-  hipLaunchKernelGGL(k_fields, dim3(blocks), dim3(256), 0, st, f, g, mask, m, nx, ny, P, bit_prev,
-                     solute, react, G, Gads1, Gads2, ax, ay, out);
+                         int nx, int ny, long long P, unsigned p1, unsigned p2, int mom,
+                         int solute, int react, float G, float Gads1, float Gads2, float ax,
+                         float ay, double* out, hipStream_t st) {
+  const int blocks = grid_for((long long)nx * ny);
+  const unsigned sb = 1u | p1 | p2;
+  if (mom)
+    hipLaunchKernelGGL(k_fields<MomSrc>, dim3(blocks), dim3(256), 0, st,
+                       MomSrc{f, mask, P, nx, ny, 1u | p2}, g, mask, m, nx, ny, P, sb, solute,
+                       react, G, Gads1, Gads2, ax, ay, out);
+  else
+    hipLaunchKernelGGL(k_fields<PopSrc>, dim3(blocks), dim3(256), 0, st, PopSrc{f, P}, g, mask, m,
+                       nx, ny, P, sb, solute, react, G, Gads1, Gads2, ax, ay, out);
   return hipGetLastError();
 }
 

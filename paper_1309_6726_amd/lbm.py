@@ -20,12 +20,14 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 FIELDS = ("rho1", "rho2", "ux", "uy", "conc", "precip", "solid")
 MAGIC = 0x4C424D5853494D31
+BLOB_VERSION = 2
+SCHEMES = {"auto": 0, "populations": 1, "moments": 2}
 
 EXPORTS = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe", "lbm_fields",
            "lbm_events", "lbm_save", "lbm_load", "lbm_set_tile", "lbm_get_tile",
-           "lbm_autotune", "lbm_set_arith", "lbm_destroy", "lbm_strerror", "lbm_last_error",
+           "lbm_autotune", "lbm_set_arith", "lbm_set_scheme", "lbm_destroy", "lbm_strerror", "lbm_last_error",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_set_tile",
-           "lbm_batch_get_tile", "lbm_batch_set_graph", "lbm_batch_step",
+           "lbm_batch_get_tile", "lbm_batch_set_scheme", "lbm_batch_set_graph", "lbm_batch_step",
            "lbm_batch_record_fronts", "lbm_batch_fronts", "lbm_batch_observe",
            "lbm_batch_fields", "lbm_batch_events", "lbm_batch_autotune", "lbm_batch_destroy",
            "surr_workspace_bytes", "surr_init", "surr_set_params", "surr_get_params",
@@ -98,6 +100,8 @@ def lib():
             "lbm_load": [P, P, C.c_size_t],
             "lbm_set_tile": [P, C.c_int32, C.c_int32],
             "lbm_set_arith": [P, C.c_int32],
+            "lbm_set_scheme": [P, C.c_int32],
+            "lbm_batch_set_scheme": [P, C.c_int32],
             "lbm_get_tile": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
             "lbm_autotune": [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                              C.POINTER(C.c_double)],
@@ -165,7 +169,7 @@ class Sim:
     workspace is a torch uint8 tensor owned by this object."""
 
     def __init__(self, p, solid, rho1, rho2, conc=None, *, device="cuda:0", stream=None,
-                 tile=None, arith=None):
+                 tile=None, arith=None, scheme=None):
         import torch
         self.p = p
         self.nx, self.ny = int(p.nx), int(p.ny)
@@ -191,6 +195,8 @@ class Sim:
             self.set_tile(*tile)
         if arith is not None:
             self.set_arith(arith)
+        if scheme is not None:
+            self.set_scheme(scheme)
 
     @classmethod
     def from_problem(cls, prob, **kw):
@@ -248,6 +254,10 @@ class Sim:
     def set_arith(self, bits: int):
         check(lib().lbm_set_arith(self.h, int(bits)))
 
+    def set_scheme(self, scheme: str):
+        """'auto' (moments at tau = 1), 'populations' or 'moments'."""
+        check(lib().lbm_set_scheme(self.h, SCHEMES[scheme]))
+
     def tile(self):
         a, b = C.c_int32(0), C.c_int32(0)
         check(lib().lbm_get_tile(self.h, C.byref(a), C.byref(b)))
@@ -274,7 +284,7 @@ def make_blob(p, f, solid, g=None, m=None, step: int = 0) -> bytes:
     react = float(p.k_r) > 0
     flags = (1 if solute else 0) | (2 if react else 0)
     solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(N)
-    parts = [struct.pack("<Q4iqq", MAGIC, nx, ny, flags, 1, int(step), 0)]
+    parts = [struct.pack("<Q4iqq", MAGIC, nx, ny, flags, BLOB_VERSION, int(step), 0)]
     ff = np.where(solid.reshape(1, ny, nx) != 0, 0.0, np.asarray(f)).astype(np.float32)
     parts.append(ff.reshape(18 * N).tobytes())
     if solute:
@@ -295,7 +305,7 @@ class Batch:
     `problems`: sequence of objects with params, solid, rho1, rho2, conc."""
 
     def __init__(self, problems, *, nslots=0, device="cuda:0", stream=None, tile=None,
-                 graph_chunk=0):
+                 graph_chunk=0, scheme=None):
         import torch
         self.n = len(problems)
         self.problems = list(problems)
@@ -333,6 +343,8 @@ class Batch:
                                        n.value, C.byref(h)))
         self._arrays = []
         self.h = h
+        if scheme is not None:
+            self.set_scheme(scheme)
         if tile is not None:
             self.set_tile(*tile)
         if graph_chunk:
@@ -351,6 +363,9 @@ class Batch:
 
     def set_tile(self, tx, sy):
         check(lib().lbm_batch_set_tile(self.h, int(tx), int(sy)))
+
+    def set_scheme(self, scheme: str):
+        check(lib().lbm_batch_set_scheme(self.h, SCHEMES[scheme]))
 
     def tile(self):
         a, b = C.c_int32(0), C.c_int32(0)

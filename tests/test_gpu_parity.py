@@ -80,20 +80,24 @@ def _random_state(nx, ny, seed, solid_frac=0.25, m_hi=0.5):
     return solid, f, g, m
 
 
+@pytest.mark.parametrize("tau", [0.9, 1.0])
 @pytest.mark.parametrize("nx,ny,tile", [(8, 8, (64, 4)), (37, 23, (64, 8)), (300, 19, (128, 16)),
                                         (509, 40, (256, 32))])
-def test_random_state_all_terms(lbm, oracle_mod, nx, ny, tile):
+def test_random_state_all_terms(lbm, oracle_mod, nx, ny, tile, tau):
     """Random non-equilibrium two-phase states with random walls and
     precipitate, every term on (forces, adhesion, body force, solute,
-    reaction, growth), ragged tiles: 30 steps, fields and events."""
-    PT.say(f"[random state] {nx}x{ny} tile {tile}")
+    reaction, growth), ragged tiles: 30 steps, fields and events.  At
+    tau = 1 the first step reads the loaded populations and stores moments;
+    the later steps rebuild the populations from moments (growth bookings
+    and mask folds included)."""
+    PT.say(f"[random state] {nx}x{ny} tile {tile} tau {tau}")
     solid, f, g, m = _random_state(nx, ny, seed=nx * 1000 + ny)
     # prime a few wall-adjacent nodes to grow within the run
     walls = sum(np.roll(solid, s, axis=a) for s in (1, -1) for a in (0, 1))
     cand = np.argwhere((solid == 0) & (walls > 0))
     for k in range(min(5, len(cand))):
         m[tuple(cand[k * len(cand) // 5])] = 0.9985 + 0.0001 * k
-    p = inputs.Params(nx=nx, ny=ny, tau=0.9, G=1.6, G_ads1=-0.33, G_ads2=0.33, tau_g=0.65,
+    p = inputs.Params(nx=nx, ny=ny, tau=tau, G=1.6, G_ads1=-0.33, G_ads2=0.33, tau_g=0.65,
                       k_r=0.01, threshold=1.0, accel_x=2e-5, accel_y=-1e-5)
     sim = lbm.Sim(p, solid, np.where(solid, 0.0, 1.0), np.where(solid, 0.0, 1.0),
                   np.zeros((ny, nx)), tile=tile)
@@ -144,13 +148,14 @@ def test_config1_events_exact_windows(lbm, oracle_mod):
     assert nev > 0
 
 
-def test_tile_shapes_bitwise_identical(lbm):
+@pytest.mark.parametrize("scheme", ["moments", "populations"])
+def test_tile_shapes_bitwise_identical(lbm, scheme):
     """The launch shape changes no result bit (reactive run with events)."""
     prob = inputs.capillary_problem(300, 40, 20, seed=5, k_r=0.01, threshold=0.4, D=0.05)
     ref = None
     for tile in [(64, 4), (128, 16), (256, 7), (64, 64), (256, 40)]:
-        PT.say(f"[tiles] {tile}")
-        sim = lbm.Sim.from_problem(prob, tile=tile)
+        PT.say(f"[tiles] {scheme} {tile}")
+        sim = lbm.Sim.from_problem(prob, tile=tile, scheme=scheme)
         sim.step(700)
         blob = sim.save()
         ev = sorted(PT.event_set(sim.events()))
@@ -164,6 +169,33 @@ def test_tile_shapes_bitwise_identical(lbm):
             N = 300 * 40
             body = 18 * N * 4 + 5 * N * 4 + N + N * 8 + N * 4 + 3 * N * 4
             assert blob[:hdr + body] == ref[0][:hdr + body], tile
+
+
+def test_schemes_agree(lbm, oracle_mod):
+    """tau = 1: populations and moments between steps give the same run to
+    FP32 rounding: fields, masses, fronts and the exact growth events."""
+    prob = inputs.capillary_problem(300, 40, 20, seed=5, k_r=0.01, threshold=0.4, D=0.05)
+    PT.say("[schemes] 300x40 reactive capillary, 1500 steps, populations vs moments")
+    a = lbm.Sim.from_problem(prob, scheme="populations")
+    b = lbm.Sim.from_problem(prob, scheme="moments")
+    for n in (1, 2, 3, 500, 1500):
+        a.step(n - a.observe()["step"])
+        b.step(n - b.observe()["step"])
+        fa, fb = a.fields(), b.fields()
+        fb = dict(fb, m=fb["precip"])
+        d = PT.compare_fields(fa, fb, m_tol=1e-6, where=f"schemes step {n}")
+        oa, ob = a.observe(), b.observe()
+        for s in range(2):
+            assert abs(oa["mass"][s] - ob["mass"][s]) <= 1e-6 * oa["mass"][s]
+        assert abs(oa["front_z"] - ob["front_z"]) <= PT.Z_TOL
+        assert oa["n_solid"] == ob["n_solid"] and oa["closure_step"] == ob["closure_step"]
+        assert PT.event_set(a.events()) == PT.event_set(b.events())
+        PT.say(f"  step {n}: {d}")
+    assert len(a.events()) > 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Sim(prob.params.replace(tau=0.9), prob.solid, prob.rho1, prob.rho2, prob.conc,
+                scheme="moments")
+    assert e.value.status == lbm.LBM_EINVAL
 
 
 def test_checkpoint_resume_bitwise(lbm):
