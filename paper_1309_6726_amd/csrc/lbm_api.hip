@@ -207,7 +207,7 @@ lbm_status queue_steps(lbm_sim* s, long long n) {
   a.threshold = p.threshold;
   for (long long t = 0; t < n; ++t) {
     const int kind = !moments ? KIND_POP : (s->mom ? KIND_MM : KIND_PM);
-    a.tx_owned = s->tx - (kind == KIND_MM ? 4 : 2);
+    a.tx_owned = kind == KIND_MM ? 60 : s->tx - 2;  // the moment step: 64-lane tiles
     a.nstrips = (p.nx + a.tx_owned - 1) / a.tx_owned;
     a.remap = (a.nstrips * a.nsegs) >= 8;
     a.fin = s->f(s->cur);
@@ -557,7 +557,7 @@ lbm_status lbm_set_arith(lbm_sim* s, int32_t bits) {
 
 lbm_status lbm_get_tile(const lbm_sim* s, int32_t* tx, int32_t* sy) {
   if (!s || !tx || !sy) return fail(LBM_EINVAL, "NULL argument");
-  *tx = s->tx;
+  *tx = use_moments(s->scheme, s->p) ? 64 : s->tx;  // moment step: 64-lane tiles
   *sy = s->sy;
   return LBM_OK;
 }
@@ -646,6 +646,7 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   int btx = s->tx, bsy = s->sy;
   float best = 1e30f;
   for (int tx : txs) {
+    if (use_moments(s->scheme, s->p) && tx != 64) continue;  // 64-lane tiles only
     if (tx > 2 * s->p.nx + 2 && tx != 64) continue;
     for (int sy : sys) {
       if (sy > 2 * s->p.ny && sy != 8) continue;
@@ -723,10 +724,11 @@ struct BatchLayout {
   int max_tiles, max_blocks;
 };
 
-// Columns a workgroup of tx threads owns: the moment step's stencil reaches
-// two columns out, the population step's one; a batch that uses the moment
-// scheme runs its first (population-in) step on the same tiling.
-int owned_cols(int tx, bool moments) { return tx - (moments ? 4 : 2); }
+// Columns a workgroup owns.  The moment step runs one wavefront (64 lanes)
+// per tile and its stencil reaches two columns out; the population step
+// reaches one.  A batch in the moment scheme runs its first
+// (population-in) step on the same 64-lane tiling.
+int owned_cols(int tx, bool moments) { return moments ? 60 : tx - 2; }
 
 int tiles_for(const lbm_params& p, int tx, int sy) {
   const int own = owned_cols(tx, true);
@@ -734,6 +736,7 @@ int tiles_for(const lbm_params& p, int tx, int sy) {
 }
 
 bool batch_moments(const lbm_batch* b) { return use_moments(b->scheme, b->p[0]); }
+int batch_tx(const lbm_batch* b) { return batch_moments(b) ? 64 : b->tx; }
 
 lbm_status batch_layout(int n, const lbm_params* p, int nslots, BatchLayout* B) {
   if (n < 1 || !p) return fail(LBM_EINVAL, "batch needs n >= 1 parameter records");
@@ -884,7 +887,7 @@ int batch_kind(const lbm_batch* b) {
 lbm_status batch_launch(lbm_batch* b, long long nsteps) {
   for (long long t = 0; t < nsteps; ++t) {
     const int kind = batch_kind(b);
-    hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, b->tx,
+    hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, batch_tx(b),
                                      b->solute, b->react, b->arith64, kind, b->stream);
     if (e != hipSuccess) {
       b->poisoned = true;
@@ -1033,9 +1036,9 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
       if (!b->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
       HIPCHECK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int t = 0; t < b->graph_chunk; ++t) {
-        hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, b->tx,
-                                         b->solute, b->react, b->arith64, batch_kind(b),
-                                         b->cap_stream);
+        hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step,
+                                         batch_tx(b), b->solute, b->react, b->arith64,
+                                         batch_kind(b), b->cap_stream);
         if (e != hipSuccess) {
           (void)hipStreamEndCapture(b->cap_stream, &g);
           if (g) (void)hipGraphDestroy(g);
@@ -1176,6 +1179,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* tx_out, int3
   int btx = b->tx, bsy = b->sy;
   float best = 1e30f;
   for (int tx : txs) {
+    if (batch_moments(b) && tx != 64) continue;  // 64-lane tiles only
     for (int sy : sys) {
       b->tx = tx;
       b->sy = sy;
@@ -1219,7 +1223,7 @@ lbm_status lbm_batch_set_scheme(lbm_batch* b, int32_t scheme) {
 
 lbm_status lbm_batch_get_tile(const lbm_batch* b, int32_t* tx, int32_t* sy) {
   if (!b || !tx || !sy) return fail(LBM_EINVAL, "NULL argument");
-  *tx = b->tx;
+  *tx = batch_tx(b);
   *sy = b->sy;
   return LBM_OK;
 }

@@ -51,6 +51,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbm_dev.h"
 
 namespace lbmdev {
@@ -102,6 +104,22 @@ __device__ __forceinline__ void sc_forces(const StepArgs& a, const R* n1, const 
   F2y = -G * rho2 * c1y - Ga2 * rho2 * csy + rho2 * ay;
 }
 
+// 1/x from the hardware estimate refined by two Newton steps (a few ulp; the
+// correctly rounded division sequence costs twice the instructions).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+
 // Equilibrium velocities of the two components (common velocity shifted by
 // tau F_s / rho_s) and the physical velocity (j + F/2) / rho that advects the
 // solute.
@@ -110,11 +128,11 @@ __device__ __forceinline__ void sc_velocities(R tau, R rho1, R rho2, R j1x, R j1
                                               R F1x, R F1y, R F2x, R F2y, R& v1x, R& v1y,
                                               R& v2x, R& v2y, R& ux, R& uy) {
   const R rt = rho1 + rho2;
-  const R irt = R(1) / rt;
+  const R irt = recip(rt);
   const R upx = (j1x + j2x) * irt, upy = (j1y + j2y) * irt;
   v1x = upx; v1y = upy; v2x = upx; v2y = upy;
-  if (rho1 > R(0)) { const R s = tau / rho1; v1x += s * F1x; v1y += s * F1y; }
-  if (rho2 > R(0)) { const R s = tau / rho2; v2x += s * F2x; v2y += s * F2y; }
+  if (rho1 > R(0)) { const R s = tau * recip(rho1); v1x += s * F1x; v1y += s * F1y; }
+  if (rho2 > R(0)) { const R s = tau * recip(rho2); v2x += s * F2x; v2y += s * F2y; }
   ux = (j1x + j2x + R(0.5) * (F1x + F2x)) * irt;
   uy = (j1y + j2y + R(0.5) * (F1y + F2y)) * irt;
 }
@@ -422,29 +440,69 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
   }
 }
 
-// Moment step (tau = 1).  Thread t holds column x0 - 2 + t.  Iteration k:
-//   A  rows ys-2+k: stored moments (fluid nodes of state n-1) and mask bytes
-//      into LDS rings; the solute populations and, at wall-adjacent nodes, the
-//      precipitate of row k-2 are requested in the same round trip;
-//   B  row k-1: incoming populations gathered from the 3x3 moments, giving
-//      rho_s and j_s; the densities go to an LDS ring (zero at solids);
-//   C  row k-2: forces from the density ring, new moments stored, solute
-//      collided, reacted and pushed, growth marks and bookings.
-// LDS: moments float[3][6][TX], densities R[3][2][TX], mask bytes u8[8][TX].
-template <bool SOLUTE, bool REACT, typename R>
-__device__ __forceinline__ void mom_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
-  const int TX = blockDim.x;
-  float* sM = (float*)lds_raw;
-  R* sR = (R*)(sM + 18 * TX);
-  uint8_t* sK = (uint8_t*)(sR + 6 * TX);
+// Cross-lane moves within one wavefront (DPP wave shifts): from_left(v) in
+// lane t is v of lane t-1, from_right(v) is v of lane t+1; the end lane
+// without a source reads 0.  Called with every lane active.
+__device__ __forceinline__ int from_left_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);  // wave_shr:1
+}
+__device__ __forceinline__ int from_right_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);  // wave_shl:1
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(from_left_i(__float_as_int(v)));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(from_right_i(__float_as_int(v)));
+}
+__device__ __forceinline__ double from_left(double v) {
+  return __hiloint2double(from_left_i(__double2hiint(v)), from_left_i(__double2loint(v)));
+}
+__device__ __forceinline__ double from_right(double v) {
+  return __hiloint2double(from_right_i(__double2hiint(v)), from_right_i(__double2loint(v)));
+}
 
+// Mask bytes of a lane and of its two neighbours packed as own | left << 8 |
+// right << 16.
+__device__ __forceinline__ unsigned pack_row_mask(unsigned m) {
+  return m | ((unsigned)from_left_i((int)m) << 8) | ((unsigned)from_right_i((int)m) << 16);
+}
+
+// Equilibrium of a link from the stored moments of its node: wr = w rho,
+// c = 1 - 3/2 |v|^2, eu = e . v  ->  w rho (1 + 3 eu + 9/2 eu^2 - 3/2 |v|^2).
+template <typename R>
+__device__ __forceinline__ R feq_m(R wr, R c, R eu) {
+  return wr * (c + eu * (R(3) + R(4.5) * eu));
+}
+
+// Moment step (tau = 1), one wavefront per workgroup: lane t holds column
+// x0 - 2 + t and the workgroup owns the 60 columns of lanes 2..61.  At
+// iteration k the lanes take the stored moments of row k (ys - 2 + k) and
+// evaluate the eight outgoing equilibria of their node (zero at nodes solid
+// in state n-1).  Each value is added to the accumulator (rho_s, j_s) of the
+// node it streams to: same lane for vertical links, the neighbouring lane
+// (DPP wave shift) for the others; a value streaming into a solid node is
+// bounced back into the sender's own accumulator on the opposite link.  Row
+// k-1 is then complete; its densities (zero at solids in state n) join a
+// three-row window held in registers, from which row k-2 is collided: forces,
+// new moments, solute, reaction and growth.
+//
+// Memory: the moments of row k+1 and the solute populations and precipitate
+// of row k-1 are copied from HBM straight into an LDS double buffer (no
+// registers held while in flight) before row k is computed, and the mask two
+// rows ahead into a register, so one iteration's arithmetic covers the next
+// iteration's memory latency.  The summation order of every node is fixed,
+// so results do not depend on the tile shape.
+template <bool SOLUTE, bool REACT, typename R>
+__device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) {
+  // prefetch slots per buffer: 0..5 moments, 6..10 solute, 11..12 precipitate
+  __shared__ float pf[2][13][64];
   const int t = threadIdx.x;
   const int nx = a.nx, ny = a.ny;
   const unsigned P = (unsigned)a.P;
   const int x0 = strip * a.tx_owned;
   const int nown = min(a.tx_owned, nx - x0);
   const bool active = t <= nown + 3;
-  const bool gatherer = t >= 1 && t <= nown + 2;
   const bool owner = t >= 2 && t <= nown + 1;
   int xc = x0 - 2 + t;
   if (xc < 0) xc += nx;
@@ -459,6 +517,7 @@ __device__ __forceinline__ void mom_tile(const StepArgs& a, int strip, int seg, 
   const float* __restrict__ Min = a.fin;
   const float* __restrict__ gin = a.gin;
   const uint8_t* __restrict__ maskp = a.mask;
+  const R WA = R(1) / R(9), WD = R(1) / R(36), WR = R(4) / R(9);
 
   auto row_y = [&](int k) {
     int yr = ys - 2 + k;
@@ -466,127 +525,200 @@ __device__ __forceinline__ void mom_tile(const StepArgs& a, int strip, int seg, 
     if (yr >= ny) yr -= ny;
     return yr;
   };
+  auto sol = [](unsigned pk, int sh, unsigned bits) { return ((pk >> sh) & bits) != 0u; };
+  auto mask_at = [&](int k) -> unsigned {
+    return (active && k < nrows) ? (unsigned)maskp[(unsigned)row_y(k) * (unsigned)nx + (unsigned)xc] : 1u;
+  };
+  using lds_ptr = __attribute__((address_space(3))) void*;
+  auto to_lds = [&](const float* src, int buf, int slot) {
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr)&pf[buf][slot][0], 4, 0, 0);
+  };
+  // copy row k's moments (fluid nodes of state n-1) and row k-2's solute
+  // and precipitate (fluid owned nodes, precipitate only next to a wall of
+  // state n) into buffer buf; the flags say which lanes copied what
+  auto prefetch = [&](int buf, int k, unsigned own_k, unsigned pkm3, unsigned pkm2,
+                      unsigned pkm1, bool& got_m, bool& got_g, bool& got_p) {
+    got_m = active && k < nrows && !(own_k & SPREV);
+    if (got_m) {
+      const unsigned i = (unsigned)row_y(k) * (unsigned)nx + (unsigned)xc;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) to_lds(Min + q * P + i, buf, q);
+    }
+    const bool crow = k >= 4 && k < nrows && owner;
+    const unsigned ownC = pkm2 & 0xFFu;
+    got_g = SOLUTE && crow && !(ownC & SPREV);
+    got_p = REACT && crow && !(ownC & SCUR) &&
+            (sol(pkm2, 16, SCUR) || sol(pkm1, 0, SCUR) || sol(pkm2, 8, SCUR) || sol(pkm3, 0, SCUR));
+    if (got_g || got_p) {
+      const unsigned i = (unsigned)(ys + k - 4) * (unsigned)nx + (unsigned)xc;
+      if (got_g) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) to_lds(gin + q * P + i, buf, 6 + q);
+      }
+      if (got_p) {
+        const float* mp = (const float*)(a.m + i);
+        to_lds(mp, buf, 11);
+        to_lds(mp + 1, buf, 12);
+      }
+    }
+  };
 
-  unsigned mk_ahead = active ? (unsigned)maskp[(unsigned)row_y(0) * (unsigned)nx + (unsigned)xc] : 1u;
-  unsigned mk0 = 1u, mk1 = 1u, mk2 = 1u;  // own mask bytes of rows k, k-1, k-2
-  R rC1 = R(0), rC2 = R(0), jC1x = R(0), jC1y = R(0), jC2x = R(0), jC2y = R(0);
-  int c0 = 0, c1 = 1, c2 = 2;  // ring slots of rows k, k-2 (= k+1 mod 3), k-1
+  // packed masks of rows k-3 .. k+1 (rows outside the tile read as solid)
+  const unsigned SOLID3 = 0x010101u;
+  unsigned pk_m3 = SOLID3, pk_m2 = SOLID3, pk_m1 = SOLID3;
+  unsigned pk_0 = pack_row_mask(mask_at(0));
+  unsigned m_ahead = mask_at(1);  // raw mask of row k+1 (then k+2)
+  bool got_m, got_g, got_p;
+  prefetch(0, 0, pk_0 & 0xFFu, pk_m3, pk_m2, pk_m1, got_m, got_g, got_p);
+
+  R acc0[6], acc1[6];  // (rho1, j1x, j1y, rho2, j2x, j2y) of rows k and k-1
+#pragma unroll
+  for (int q = 0; q < 6; ++q) { acc0[q] = R(0); acc1[q] = R(0); }
+  R rC[6];  // complete (rho, j) of row k-2
+#pragma unroll
+  for (int q = 0; q < 6; ++q) rC[q] = R(0);
+  // density window (zero at solids of state n): centre, from left, from right
+  R W1[6], W2[6];  // rows k-2, k-3: (c1, c2, l1, l2, r1, r2)
+#pragma unroll
+  for (int q = 0; q < 6; ++q) { W1[q] = R(0); W2[q] = R(0); }
 
   for (int k = 0; k < nrows; ++k) {
-    // ---- requests: moments of row k, mask of row k+1, solute of row k-2 ---
-    mk0 = mk_ahead;
-    float mv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (active) {
-      const unsigned ida = (unsigned)row_y(k) * (unsigned)nx + (unsigned)xc;
-      if (!(mk0 & SPREV)) {
-#pragma unroll
-        for (int q = 0; q < 6; ++q) mv[q] = Min[q * P + ida];
-      }
-      if (k + 1 < nrows) mk_ahead = maskp[(unsigned)row_y(k + 1) * (unsigned)nx + (unsigned)xc];
-    } else {
-      mk0 = 1u;
-    }
+    const int buf = k & 1;
+    // everything requested during the previous iteration has arrived
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
+    const unsigned pk_p1 = pack_row_mask(m_ahead);
+    // what the data in buffer buf holds (lanes that did not copy read 0)
+    const bool cur_m = got_m, cur_g = got_g, cur_p = got_p;
+    auto take = [&](int slot, bool got) {
+      const float v = pf[buf][slot][t];  // read unconditionally, then select
+      return got ? v : 0.0f;
+    };
+    const unsigned own0 = pk_0 & 0xFFu;
+    // requests for the next iteration: row k+1's moments, row k-1's solute,
+    // the mask of row k+2
+    prefetch(buf ^ 1, k + 1, pk_p1 & 0xFFu, pk_m2, pk_m1, pk_0, got_m, got_g, got_p);
+    m_ahead = mask_at(k + 2);
+
     const bool crow = k >= 4 && owner;
     const int yC = ys + k - 4;
     const unsigned idxC = (unsigned)(crow ? yC : 0) * (unsigned)nx + (unsigned)xc;
-    float gv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    double mC = 0.0;
-    if (crow) {
-      if (SOLUTE && !(mk2 & SPREV)) {
+    const unsigned ownC = pk_m2 & 0xFFu;
+
+    // links of this node whose target is solid in state n-1 (bit i = link i)
+    const unsigned bb =
+        (sol(pk_0, 16, SPREV) ? 0x02u : 0u) | (sol(pk_p1, 0, SPREV) ? 0x04u : 0u) |
+        (sol(pk_0, 8, SPREV) ? 0x08u : 0u) | (sol(pk_m1, 0, SPREV) ? 0x10u : 0u) |
+        (sol(pk_p1, 16, SPREV) ? 0x20u : 0u) | (sol(pk_p1, 8, SPREV) ? 0x40u : 0u) |
+        (sol(pk_m1, 8, SPREV) ? 0x80u : 0u) | (sol(pk_m1, 16, SPREV) ? 0x100u : 0u);
+    const bool bounce = bb != 0u && !(own0 & SPREV);
+
+    // ---- sources of row k: outgoing equilibria, streamed -----------------
+    R accN[6];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) gv[q] = gin[q * P + idxC];
-      }
-      if (REACT && !(mk2 & SCUR)) {
-        const int kb = ((k - 3) & 7) * TX, km = ((k - 2) & 7) * TX, ka = ((k - 1) & 7) * TX;
-        const bool wall = ((sK[km + t + 1] | sK[ka + t] | sK[km + t - 1] | sK[kb + t]) & SCUR) != 0;
-        if (wall) mC = a.m[idxC];
+    for (int c = 0; c < 2; ++c) {
+      // with u3 = 3 v: w rho (1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v^2)
+      //              = w rho (cc + e3 (1 + e3 / 2)), e3 = e . u3, cc = 1 - u3^2 / 6
+      const R rho = (R)take(3 * c, cur_m);
+      const R ux = R(3) * (R)take(3 * c + 1, cur_m), uy = R(3) * (R)take(3 * c + 2, cur_m);
+      const R cc = fmar(ux * ux + uy * uy, R(-1) / R(6), R(1));
+      const R ra = WA * rho, rd = WD * rho;
+      auto out = [&](R r, R e3) { return r * fmar(e3, fmar(e3, R(0.5), R(1)), cc); };
+      const R o0 = WR * rho * cc;
+      const R o1 = out(ra, ux), o2 = out(ra, uy), o3 = out(ra, -ux), o4 = out(ra, -uy);
+      const R o5 = out(rd, ux + uy), o6 = out(rd, uy - ux), o7 = out(rd, -ux - uy),
+              o8 = out(rd, ux - uy);
+      // up links (2, 5, 6) start the accumulator of row k+1
+      const R a5 = from_left(o5), a6 = from_right(o6);
+      const R up = (o2 + a5) + a6;
+      accN[3 * c] = up;
+      accN[3 * c + 1] = a5 - a6;
+      accN[3 * c + 2] = up;
+      // rest and horizontal links (1, 3) into row k
+      const R a1 = from_left(o1), a3 = from_right(o3);
+      acc0[3 * c] += (o0 + a1) + a3;
+      acc0[3 * c + 1] += a1 - a3;
+      // down links (4, 7, 8) complete row k-1
+      const R a7 = from_right(o7), a8 = from_left(o8);
+      const R dn = (o4 + a7) + a8;
+      acc1[3 * c] += dn;
+      acc1[3 * c + 1] += a8 - a7;
+      acc1[3 * c + 2] -= dn;
+      // values streaming into a node solid in state n-1 bounce back into the
+      // sender's opposite link: rho += o_i, j -= e_i o_i
+      if (bounce) {
+        const R s1 = (R)((bb >> 1) & 1u), s2 = (R)((bb >> 2) & 1u), s3 = (R)((bb >> 3) & 1u),
+                s4 = (R)((bb >> 4) & 1u), s5 = (R)((bb >> 5) & 1u), s6 = (R)((bb >> 6) & 1u),
+                s7 = (R)((bb >> 7) & 1u), s8 = (R)((bb >> 8) & 1u);
+        R br = s1 * o1, bx = s3 * o3, by = s4 * o4;
+        br = fmar(s2, o2, br); br = fmar(s3, o3, br);
+        br = fmar(s4, o4, br); br = fmar(s5, o5, br);
+        br = fmar(s6, o6, br); br = fmar(s7, o7, br);
+        br = fmar(s8, o8, br);
+        bx = fmar(-s1, o1, bx); bx = fmar(-s5, o5, bx);
+        bx = fmar(s6, o6, bx); bx = fmar(s7, o7, bx);
+        bx = fmar(-s8, o8, bx);
+        by = fmar(-s2, o2, by); by = fmar(-s5, o5, by);
+        by = fmar(-s6, o6, by); by = fmar(s7, o7, by);
+        by = fmar(s8, o8, by);
+        acc0[3 * c] += br;
+        acc0[3 * c + 1] += bx;
+        acc0[3 * c + 2] += by;
       }
     }
-    __builtin_amdgcn_s_waitcnt(VMCNT0);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) sM[(c0 * 6 + q) * TX + t] = mv[q];
-    sK[(k & 7) * TX + t] = (uint8_t)mk0;
-    lds_barrier(TX);
 
-    // ---- B: gather row k-1 -------------------------------------------------
-    R rN1 = R(0), rN2 = R(0), jN1x = R(0), jN1y = R(0), jN2x = R(0), jN2y = R(0);
-    if (k >= 2 && gatherer) {
-      if (!(mk1 & SPREV)) {
-        const int kB = ((k - 2) & 7) * TX, kM = ((k - 1) & 7) * TX, kA = (k & 7) * TX;
-        // upstream node x - e_i of link i: 1 W, 2 S, 3 E, 4 N, 5 SW, 6 SE, 7 NE, 8 NW
-        const int mc[9] = {t, t - 1, t, t + 1, t, t - 1, t + 1, t + 1, t - 1};
-        const int ms[9] = {c2, c2, c1, c2, c0, c1, c1, c0, c0};
-        const int ks[9] = {kM, kM, kB, kM, kA, kB, kB, kA, kA};
-        bool up[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) up[i] = !(sK[ks[i] + mc[i]] & SPREV);
-        float r[9], vx[9], vy[9];
-        R fl[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          r[i] = sM[(ms[i] * 6 + 0) * TX + mc[i]];
-          vx[i] = sM[(ms[i] * 6 + 1) * TX + mc[i]];
-          vy[i] = sM[(ms[i] * 6 + 2) * TX + mc[i]];
-        }
-        gather_links<R>(r, vx, vy, up, fl);
-        moments9<R>(fl, rN1, jN1x, jN1y);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          r[i] = sM[(ms[i] * 6 + 3) * TX + mc[i]];
-          vx[i] = sM[(ms[i] * 6 + 4) * TX + mc[i]];
-          vy[i] = sM[(ms[i] * 6 + 5) * TX + mc[i]];
-        }
-        gather_links<R>(r, vx, vy, up, fl);
-        moments9<R>(fl, rN2, jN2x, jN2y);
-      }
-      const bool sol = (mk1 & SCUR) != 0;
-      sR[(c2 * 2 + 0) * TX + t] = sol ? R(0) : rN1;
-      sR[(c2 * 2 + 1) * TX + t] = sol ? R(0) : rN2;
+    // ---- row k-1 complete: density window --------------------------------
+    R W0[6];
+    {
+      const bool s1 = sol(pk_m1, 0, SCUR);
+      const R d1 = s1 ? R(0) : acc1[0], d2 = s1 ? R(0) : acc1[3];
+      W0[0] = d1; W0[1] = d2;
+      W0[2] = from_left(d1); W0[3] = from_left(d2);
+      W0[4] = from_right(d1); W0[5] = from_right(d2);
     }
-    lds_barrier(TX);
 
-    // ---- C: collide row k-2 ------------------------------------------------
+    // ---- collide row k-2 ---------------------------------------------------
     bool ev = false;
     int evx = 0, evy = 0;
     if (crow) {
       const int y = yC;
       const unsigned idx = idxC;
-      if (mk2 & SCUR) {
+      float gv[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) gv[q] = take(6 + q, cur_g);
+      if (ownC & SCUR) {
         if (REACT) {
-          if (mk2 & a.bit_p1) {
+          if (ownC & a.bit_p1) {
             // turned solid at the end of the previous step: book what it carried
-            a.drop[idx] = (float)rC1;
-            a.drop[P + idx] = (float)rC2;
+            a.drop[idx] = (float)rC[0];
+            a.drop[P + idx] = (float)rC[3];
             a.drop[2 * P + idx] =
                 SOLUTE ? (float)((((R)gv[0] + (R)gv[1]) + ((R)gv[2] + (R)gv[3])) + (R)gv[4]) : 0.0f;
-          } else if (mk2 & a.bit_p2) {
+          } else if (ownC & a.bit_p2) {
             a.mask[idx] = 1;  // booked one step ago: fold the mark into bit0
           }
         }
       } else {
-        const int kb = ((k - 3) & 7) * TX, km = ((k - 2) & 7) * TX, ka = ((k - 1) & 7) * TX;
-        // neighbours x + e_i in link order 1..8 = E, N, W, S, NE, NW, SW, SE
-        const int nc[9] = {t, t + 1, t, t - 1, t, t + 1, t - 1, t - 1, t + 1};
-        const int nsl[9] = {c1, c1, c2, c1, c0, c2, c2, c0, c0};
-        const int nk[9] = {km, km, ka, km, kb, ka, ka, kb, kb};
+        // neighbours x + e_i, link order 1..8 = E, N, W, S, NE, NW, SW, SE
         R n1[9], n2[9];
         float sf[9];
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-          n1[i] = sR[(nsl[i] * 2 + 0) * TX + nc[i]];
-          n2[i] = sR[(nsl[i] * 2 + 1) * TX + nc[i]];
-          sf[i] = (sK[nk[i] + nc[i]] & SCUR) ? 1.0f : 0.0f;
-        }
+        n1[1] = W1[4]; n2[1] = W1[5]; sf[1] = sol(pk_m2, 16, SCUR) ? 1.0f : 0.0f;
+        n1[2] = W0[0]; n2[2] = W0[1]; sf[2] = sol(pk_m1, 0, SCUR) ? 1.0f : 0.0f;
+        n1[3] = W1[2]; n2[3] = W1[3]; sf[3] = sol(pk_m2, 8, SCUR) ? 1.0f : 0.0f;
+        n1[4] = W2[0]; n2[4] = W2[1]; sf[4] = sol(pk_m3, 0, SCUR) ? 1.0f : 0.0f;
+        n1[5] = W0[4]; n2[5] = W0[5]; sf[5] = sol(pk_m1, 16, SCUR) ? 1.0f : 0.0f;
+        n1[6] = W0[2]; n2[6] = W0[3]; sf[6] = sol(pk_m1, 8, SCUR) ? 1.0f : 0.0f;
+        n1[7] = W2[2]; n2[7] = W2[3]; sf[7] = sol(pk_m3, 8, SCUR) ? 1.0f : 0.0f;
+        n1[8] = W2[4]; n2[8] = W2[5]; sf[8] = sol(pk_m3, 16, SCUR) ? 1.0f : 0.0f;
         R F1x, F1y, F2x, F2y;
-        sc_forces<R>(a, n1, n2, sf, rC1, rC2, F1x, F1y, F2x, F2y);
+        sc_forces<R>(a, n1, n2, sf, rC[0], rC[3], F1x, F1y, F2x, F2y);
         R v1x, v1y, v2x, v2y, ux, uy;
-        sc_velocities<R>((R)a.tau, rC1, rC2, jC1x, jC1y, jC2x, jC2y, F1x, F1y, F2x, F2y, v1x, v1y,
-                         v2x, v2y, ux, uy);
+        sc_velocities<R>((R)a.tau, rC[0], rC[3], rC[1], rC[2], rC[4], rC[5], F1x, F1y, F2x, F2y,
+                         v1x, v1y, v2x, v2y, ux, uy);
         float* __restrict__ fo = a.fout;
-        fo[idx] = (float)rC1;
+        fo[idx] = (float)rC[0];
         fo[P + idx] = (float)v1x;
         fo[2 * P + idx] = (float)v1y;
-        fo[3 * P + idx] = (float)rC2;
+        fo[3 * P + idx] = (float)rC[3];
         fo[4 * P + idx] = (float)v2x;
         fo[5 * P + idx] = (float)v2y;
         if (SOLUTE) {
@@ -594,22 +726,32 @@ __device__ __forceinline__ void mom_tile(const StepArgs& a, int strip, int seg, 
           const int yu = y == ny - 1 ? 0 : y + 1;
           const unsigned iE = (unsigned)y * nx + xr, iW = (unsigned)y * nx + xl;
           const unsigned iN = (unsigned)yu * nx + xc, iS = (unsigned)yd * nx + xc;
-          solute_step<REACT, R>(a, gv, ux, uy, rC1, rC2, sf, mC, P, idx, iE, iN, iW, iS, xc, y, ev,
-                                evx, evy);
+          const double mC =
+              cur_p ? __hiloint2double(__float_as_int(pf[buf][12][t]), __float_as_int(pf[buf][11][t]))
+                    : 0.0;
+          solute_step<REACT, R>(a, gv, ux, uy, rC[0], rC[3], sf, mC, P, idx, iE, iN, iW, iS, xc,
+                                y, ev, evx, evy);
         }
       }
     }
     if (REACT) log_events(a, ev, evx, evy);
-    // rotate the register pipeline and the ring slots
-    rC1 = rN1; rC2 = rN2;
-    jC1x = jN1x; jC1y = jN1y; jC2x = jN2x; jC2y = jN2y;
-    mk2 = mk1;
-    mk1 = mk0;
-    const int cz = c0;
-    c0 = c1;
-    c1 = c2;
-    c2 = cz;
+
+    // ---- rotate ------------------------------------------------------------
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      rC[q] = acc1[q];
+      acc1[q] = acc0[q];
+      acc0[q] = accN[q];
+      W2[q] = W1[q];
+      W1[q] = W0[q];
+    }
+    pk_m3 = pk_m2;
+    pk_m2 = pk_m1;
+    pk_m1 = pk_0;
+    pk_0 = pk_p1;
   }
+  // drain: no request may still be writing this wavefront's LDS at exit
+  __builtin_amdgcn_s_waitcnt(VMCNT0);
 }
 
 // XCD-aware order: the hardware hands block b to XCD b mod 8, so XCD x
@@ -624,7 +766,7 @@ __host__ __device__ inline int xcd_tile(int b, int T) {
 template <bool SOLUTE, bool REACT, typename R, int KIND>
 __device__ __forceinline__ void run_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
   if (KIND == KIND_MM)
-    mom_tile<SOLUTE, REACT, R>(a, strip, seg, lds_raw);
+    mom_wave<SOLUTE, REACT, R>(a, strip, seg);
   else
     step_tile<SOLUTE, REACT, R, KIND == KIND_PM>(a, strip, seg, lds_raw);
 }
@@ -1043,7 +1185,7 @@ __global__ void k_unpack(MomSrc src, float* __restrict__ fout) {
 // ---- launchers ------------------------------------------------------------
 size_t step_lds_bytes(int kind, int tx, int arith64) {
   const size_t r = arith64 ? sizeof(double) : sizeof(float);
-  if (kind == KIND_MM) return (size_t)tx * (18 * sizeof(float) + 6 * r + 8);
+  if (kind == KIND_MM) return 0;  // registers and cross-lane moves only
   return (size_t)4 * tx * (2 * r + sizeof(float));
 }
 
@@ -1059,6 +1201,7 @@ void launch_step_t(const StepArgs& a, int T, int tx, size_t lds, hipStream_t st)
 
 hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, hipStream_t st) {
   const int T = a.nstrips * a.nsegs;
+  if (kind == KIND_MM) tx = 64;  // the moment step runs one wavefront per tile
   const size_t lds = step_lds_bytes(kind, tx, arith64);
   if (arith64) {
     if (kind == KIND_MM) launch_step_t<double, KIND_MM>(a, T, tx, lds, st);
@@ -1086,6 +1229,7 @@ void launch_batch_t(const StepArgs* insts, const int4* tiles, int ntiles, const 
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
                              const long long* stepc, int tx, int solute, int react, int arith64,
                              int kind, hipStream_t st) {
+  if (kind == KIND_MM) tx = 64;
   const size_t lds = step_lds_bytes(kind, tx, arith64);
   if (arith64) {
     if (kind == KIND_MM) launch_batch_t<double, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
