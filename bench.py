@@ -2,9 +2,11 @@
 
 Workload: the 2048x2048 synthetic porous carbon preform (RSA disks of radius
 8-24, solid fraction 0.5, wetting reservoir on the left 64 columns, D2Q5
-solute with D=0.05, reaction k_r=1e-3, threshold 1), FP32 populations.  One
-step = one full lattice Boltzmann time step (flow + solute + reaction +
-growth) over all 4,194,304 nodes.  Prints one JSON line.
+solute with D=0.05, reaction k_r=1e-3, threshold 1, tau=1).  One step = one
+full lattice Boltzmann time step (flow + solute + reaction + growth) over all
+4,194,304 nodes.  At tau = 1 the library keeps six FP32 moments per node
+between steps (the moment scheme); the population scheme (eighteen FP32
+populations per node) is timed beside it.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -35,25 +37,33 @@ def wall_adjacent(solid: np.ndarray) -> np.ndarray:
     return (~s) & (n > 0)
 
 
-BYTES_PER_LUP = 185   # 2x9 flow + 5 solute FP32 populations read and written, 1 mask byte
+# Algorithmic HBM bytes per lattice update.  Population scheme: 2x9 flow and 5
+# solute FP32 populations read and written, 1 mask byte.  Moment scheme: 2x3
+# flow moments (rho_s, v_s) and 5 solute populations read and written, 1 mask
+# byte.
+BYTES_PER_LUP = {"populations": 185, "moments": 89}
 BYTES_PER_WALL_NODE = 16  # FP64 precipitate read and written at wall-adjacent fluid nodes
+KERNEL = {"populations": "k_step<true,true,double,KIND_POP>",
+          "moments": "k_step<true,true,double,KIND_MM>"}
 
 
-def algorithmic_bytes(solid: np.ndarray) -> tuple:
-    """Algorithmic HBM bytes of one step: 185 B per lattice update (all nodes,
-    the unit MLUPS counts) plus 16 B per wall-adjacent fluid node.  Also the
-    fluid-only figure (solid nodes touch only their mask byte)."""
+def algorithmic_bytes(solid: np.ndarray, scheme: str) -> tuple:
+    """Algorithmic HBM bytes of one step: the per-update figure of the scheme
+    over all nodes (the unit MLUPS counts) plus 16 B per wall-adjacent fluid
+    node.  Also the fluid-only figure (solid nodes touch only their mask
+    byte)."""
+    b = BYTES_PER_LUP[scheme]
     fluid = int(np.count_nonzero(solid == 0))
     wall = int(np.count_nonzero(wall_adjacent(solid)))
-    per_lup = BYTES_PER_LUP * solid.size + BYTES_PER_WALL_NODE * wall
-    fluid_only = (BYTES_PER_LUP - 1) * fluid + solid.size + BYTES_PER_WALL_NODE * wall
+    per_lup = b * solid.size + BYTES_PER_WALL_NODE * wall
+    fluid_only = (b - 1) * fluid + solid.size + BYTES_PER_WALL_NODE * wall
     return per_lup, fluid_only, wall
 
 
-def measured_traffic(tile):
+def measured_traffic(tile, scheme):
     """HBM bytes per launch from the committed PMC summary, only if it was
-    taken on this kernel source and launch shape."""
-    path = os.path.join(ROOT, "profiles", "k_step_preform2048_traffic.json")
+    taken on this kernel source, scheme and launch shape."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{scheme}_preform2048_traffic.json")
     src = os.path.join(ROOT, "paper_1309_6726_amd", "csrc", "lbm_kernels.hip")
     try:
         with open(path) as fh:
@@ -63,6 +73,8 @@ def measured_traffic(tile):
     except OSError:
         return None
     if rec.get("kernel_src_sha256") != sha or list(rec.get("tile", [])) != list(tile):
+        return None
+    if rec.get("kernel") != KERNEL[scheme]:
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -189,6 +201,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--tile", type=str, default="auto", help="TXxSY or auto")
+    ap.add_argument("--scheme", choices=("auto", "moments", "populations"), default="auto",
+                    help="state between steps (auto: moments at tau = 1)")
+    ap.add_argument("--compare-steps", type=int, default=1000,
+                    help="steps of the other scheme timed for comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--no-sweep", action="store_true", help="skip the capillary sweep")
@@ -223,30 +239,55 @@ def main():
     prob = inputs.config2(seed=0)
     p = prob.params
     N = p.nx * p.ny
+    scheme = args.scheme
+    if scheme == "auto":
+        scheme = "moments" if float(p.tau) == 1.0 else "populations"
     stream = torch.cuda.Stream(device=dev)
-    with torch.cuda.stream(stream):
-        sim = lbm.Sim.from_problem(prob, device=dev, stream=stream)
-        if args.tile == "auto":
+
+    def timed_run(scheme, steps, warmup, tile):
+        """Autotune (or set) the launch shape, warm up, time `steps` steps
+        with HIP events on the library's stream."""
+        sim = lbm.Sim.from_problem(prob, device=dev, stream=stream, scheme=scheme)
+        if tile == "auto":
             (tx, sy), _ = sim.autotune(steps=10)
         else:
-            tx, sy = (int(v) for v in args.tile.lower().split("x"))
+            tx, sy = (int(v) for v in tile.lower().split("x"))
             sim.set_tile(tx, sy)
-        sim.step(args.warmup)
+            tx, sy = sim.tile()
+        sim.step(warmup)
         o0 = sim.observe()
-        bytes0 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8))
+        b0 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8), scheme)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record(stream)
-        sim.step(args.steps)
+        sim.step(steps)
         e1.record(stream)
         e1.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
         o1 = sim.observe()
-        bytes1 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8))
+        b1 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8), scheme)
+        del sim
+        return (tx, sy), ms, wall, o0, o1, b0, b1
+
+    with torch.cuda.stream(stream):
+        (tx, sy), ms, wall, o0, o1, bytes0, bytes1 = timed_run(scheme, args.steps, args.warmup,
+                                                              args.tile)
+        compare = None
+        if args.compare_steps > 0:
+            other = "populations" if scheme == "moments" else "moments"
+            if other == "populations" or float(p.tau) == 1.0:
+                ctile, cms, _, _, _, cb0, cb1 = timed_run(other, args.compare_steps, 20, "auto")
+                cstep = cms / args.compare_steps
+                cbytes = 0.5 * (cb0[0] + cb1[0])
+                compare = {"scheme": other, "kernel": KERNEL[other], "tile": list(ctile),
+                           "steps": args.compare_steps, "ms_per_step": round(cstep, 5),
+                           "mlups": round(N / (cstep / 1e3) / 1e6, 1),
+                           "bytes_per_lup": BYTES_PER_LUP[other],
+                           "achieved_gbs": round(cbytes / (cstep / 1e3) / 1e9, 1)}
     copy_gbs = copy_bandwidth(torch, dev)
     ms_step = ms / args.steps
     mlups = N * args.steps / (ms / 1e3) / 1e6
@@ -254,7 +295,7 @@ def main():
     per_launch = 0.5 * (bytes0[0] + bytes1[0])
     fluid_only = 0.5 * (bytes0[1] + bytes1[1])
     achieved = per_launch / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic((tx, sy))
+    traffic = measured_traffic((tx, sy), scheme)
     cons = abs(o1["solute"] + o1["precipitate"] + o1["solute_removed"] -
                (o0["solute"] + o0["precipitate"] + o0["solute_removed"]))
     out = {
@@ -268,13 +309,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "porous preform 2048x2048, RSA disks r=8..24, solid fraction "
                                f"{prob.solid_fraction:.3f}, reservoir 64 cols, D2Q5 D=0.05, "
                                "k_r=1e-3, threshold 1, 2-component Shan-Chen D2Q9 tau=1, "
-                               "FP32 populations, FP64 arithmetic",
-                   "nx": p.nx, "ny": p.ny, "tile": [tx, sy],
+                               f"FP32 state ({scheme}), FP64 arithmetic",
+                   "nx": p.nx, "ny": p.ny, "tile": [tx, sy], "scheme": scheme,
                    "mflups_fluid": round(fluid0 * args.steps / (ms / 1e3) / 1e6, 1),
                    "wall_adjacent_nodes": bytes0[2],
                    "events_in_run": int(o1["n_events"] - o0["n_events"]),
@@ -285,12 +326,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else int(traffic),
-                     "kernel": "k_step<true,true,double>",
-                     "bytes_per_lup": BYTES_PER_LUP,
+                     "kernel": KERNEL[scheme],
+                     "bytes_per_lup": BYTES_PER_LUP[scheme],
                      "algorithmic_bytes_per_launch": int(per_launch),
                      "avg_launch_ms": round(ms_step, 5)},
     }
-    del sim
+    if compare is not None:
+        out["other_scheme"] = compare
     if not args.no_sweep:
         out["sweep"] = sweep_section(args, torch, dev)
     if not args.no_surrogate:
