@@ -88,6 +88,15 @@ typedef struct {
   int64_t n_events;          /* number of growth events so far */
   int32_t nonfinite;         /* 1 if any fluid density/concentration is NaN/Inf */
   int32_t pad;
+  /* Radii of the capillary section (section "Results and discussion", Fig. 4),
+     each equal to W for the unreacted slit; NaN if W == 0.  With w(x) the
+     fluid nodes of column x between the walls and A = sum w the open area:
+     r_min = min w, r_ave = A / L (L = x_out - x_in), and the hydraulic radius
+     r_h = A / P, P the length of the lower wall's profile (one unit per column
+     plus the vertical steps between neighbouring columns).  The effective
+     radius of Eq. (1) needs a front time series and a run without reaction:
+     see paper_1309_6726_amd/radii.py. */
+  double r_min, r_ave, r_h;
 } lbm_obs;
 
 /* A growth event: node (x, y) is solid from state `step` on. */

@@ -65,6 +65,7 @@ typedef struct {
   int64_t n_solid, n_events;
   int32_t nonfinite;
   int32_t pad;
+  double r_min, r_ave, r_h; /* capillary radii (Fig. 4), NaN without a capillary */
 } orc_obs;
 
 typedef struct {
@@ -519,6 +520,7 @@ void orc_observe(orc_sim *sim, orc_obs *o) {
   o->front_z = NAN;
   o->delta_e = 0;
   o->closure_step = -1;
+  o->r_min = o->r_ave = o->r_h = NAN;
   if (p->W <= 0) return;
 
   /* centre row(s) */
@@ -579,4 +581,28 @@ void orc_observe(orc_sim *sim, orc_obs *o) {
   }
   o->delta_e = de;
   o->closure_step = closure;
+
+  /* Radii of the capillary section (section "Results and discussion", Fig. 4),
+   * all equal to the width W for the unreacted slit: with w(x) the fluid nodes
+   * of column x between the walls and h(x) the solid grown on the lower wall,
+   * r_min = min w, r_ave = A / L with A = sum w the open area, and the
+   * hydraulic radius r_h = A / P with P the length of the lower wall's
+   * profile: one lattice unit per column plus the vertical steps
+   * |h(x+1) - h(x)| between neighbouring columns. */
+  const long L = p->x_out - p->x_in;
+  double area = 0, wmin = p->W, steps = 0;
+  int hprev = 0;
+  for (long x = p->x_in; x < p->x_out; x++) {
+    int w = 0, h = 0;
+    for (int y = p->y0; y < p->y0 + p->W; y++)
+      if (!sim->s[(long)y * p->nx + x]) w++;
+    while (h < p->W && sim->s[(long)(p->y0 + h) * p->nx + x]) h++;
+    area += w;
+    if (w < wmin) wmin = w;
+    if (x > p->x_in) steps += abs(h - hprev);
+    hprev = h;
+  }
+  o->r_min = wmin;
+  o->r_ave = area / (double)L;
+  o->r_h = area / ((double)L + steps);
 }

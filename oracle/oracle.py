@@ -51,7 +51,8 @@ class _Obs(C.Structure):
                 ("front_z", C.c_double), ("delta_e", C.c_double),
                 ("closure_step", C.c_int64), ("n_solid", C.c_int64),
                 ("n_events", C.c_int64), ("nonfinite", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pad", C.c_int32), ("r_min", C.c_double), ("r_ave", C.c_double),
+                ("r_h", C.c_double)]
 
 
 _lib = None
@@ -196,7 +197,7 @@ class Oracle:
                 "solute_removed": o.solute_removed, "front_z": o.front_z,
                 "delta_e": o.delta_e, "closure_step": o.closure_step,
                 "n_solid": o.n_solid, "n_events": o.n_events,
-                "nonfinite": o.nonfinite}
+                "nonfinite": o.nonfinite, "r_min": o.r_min, "r_ave": o.r_ave, "r_h": o.r_h}
 
     def events(self) -> np.ndarray:
         L = lib()

@@ -240,6 +240,26 @@ size_t blob_size(const lbm_sim* s, long long nev) {
   return n;
 }
 
+// Capillary observables from the observer's output: front, growth, closure
+// and the radii of Fig. 4 (r_min, r_ave = A / L, r_h = A / P with P the
+// lower wall's profile length: one unit per column plus its vertical steps).
+void capillary_radii(const lbm_params& p, const double* h, lbm_obs* o) {
+  if (p.W > 0) {
+    const double L = (double)(p.x_out - p.x_in);
+    o->front_z = h[OBS_SLOTS];
+    o->delta_e = h[OBS_SLOTS + 1];
+    o->closure_step = (int64_t)h[OBS_SLOTS + 2];
+    o->r_min = h[OBS_SLOTS + 4];
+    o->r_ave = h[OBS_SLOTS + 3] / L;
+    o->r_h = h[OBS_SLOTS + 3] / (L + h[OBS_SLOTS + 5]);
+  } else {
+    o->front_z = NAN;
+    o->delta_e = 0.0;
+    o->closure_step = -1;
+    o->r_min = o->r_ave = o->r_h = NAN;
+  }
+}
+
 lbm_status copy_planes_d2h(char* dst, const char* src_dev, int planes, long long N, long long P,
                            size_t esz, hipStream_t st) {
   for (int q = 0; q < planes; ++q)
@@ -371,15 +391,7 @@ lbm_status lbm_observe(lbm_sim* s, lbm_obs* o) {
   o->n_solid = (int64_t)h[7];
   o->nonfinite = h[8] > 0.0;
   o->n_events = (int64_t)nev;
-  if (p.W > 0) {
-    o->front_z = h[OBS_SLOTS];
-    o->delta_e = h[OBS_SLOTS + 1];
-    o->closure_step = (int64_t)h[OBS_SLOTS + 2];
-  } else {
-    o->front_z = NAN;
-    o->delta_e = 0.0;
-    o->closure_step = -1;
-  }
+  capillary_radii(p, h, o);
   if ((long long)nev > s->L.ev_cap)
     return fail(LBM_EDEVICE, "event log overflow (%llu > %lld)", nev, s->L.ev_cap);
   if (o->nonfinite) {
@@ -1111,9 +1123,7 @@ lbm_status lbm_batch_observe(lbm_batch* b, int32_t i, lbm_obs* o) {
   o->n_solid = (int64_t)h[7];
   o->nonfinite = h[8] > 0.0;
   o->n_events = (int64_t)nev;
-  o->front_z = p.W > 0 ? h[OBS_SLOTS] : NAN;
-  o->delta_e = p.W > 0 ? h[OBS_SLOTS + 1] : 0.0;
-  o->closure_step = p.W > 0 ? (int64_t)h[OBS_SLOTS + 2] : -1;
+  capillary_radii(p, h, o);
   if (o->nonfinite) {
     b->poisoned = true;
     return fail(LBM_ENONFINITE, "instance %d holds a NaN/Inf at step %lld", i, b->step);

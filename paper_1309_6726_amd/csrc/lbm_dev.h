@@ -10,7 +10,7 @@
 namespace lbmdev {
 
 constexpr int OBS_SLOTS = 9;   // per-block partial sums of the observe reduction
-constexpr int OBS_OUT = OBS_SLOTS + 3;
+constexpr int OBS_OUT = OBS_SLOTS + 6;  // + capillary: z, delta_e, closure, area, min width, steps
 
 struct StepArgs {
   const float* fin;

@@ -980,8 +980,11 @@ __global__ void k_obs_final(const double* __restrict__ partial, int nblocks, dou
 }
 
 // Capillary observables computed by one workgroup of 256 threads: centreline
-// front, largest grown width and first closure.  out: [0] z, [1] delta_e,
-// [2] closure step (-1 if none).  sb: solid bits of state n.
+// front, largest grown width, first closure, and the sums behind the radii of
+// Fig. 4.  out: [0] z, [1] delta_e, [2] closure step (-1 if none), [3] open
+// area A (fluid nodes between the walls), [4] narrowest open column, [5] sum
+// over neighbouring columns of |h(x+1) - h(x)|, h the growth on the lower
+// wall.  sb: solid bits of state n.
 template <typename Src>
 __device__ void capillary_obs(const Src& src, const uint8_t* __restrict__ mask,
                               const int32_t* __restrict__ sstep, int nx, unsigned sb, int x_in,
@@ -989,11 +992,13 @@ __device__ void capillary_obs(const Src& src, const uint8_t* __restrict__ mask,
   __shared__ int s_min[256];
   __shared__ double s_de[256];
   __shared__ long long s_cl[256];
+  __shared__ int s_area[256], s_wmin[256], s_steps[256];
   const int nr = (W % 2 == 0) ? 2 : 1;
   const int row0 = (W % 2 == 0) ? (y0 + W / 2 - 1) : (y0 + (W - 1) / 2);
   int best = x_out;  // first x where the scan stops
   double de = 0.0;
   long long cl = -1;
+  int area = 0, wmin = W, steps = 0;
   for (int x = x_in + threadIdx.x; x < x_out; x += blockDim.x) {
     // front predicate at x
     bool blocked = false, nblocked = false;
@@ -1019,6 +1024,15 @@ __device__ void capillary_obs(const Src& src, const uint8_t* __restrict__ mask,
     int db = 0, dt = 0;
     while (db < W && (mask[(long long)(y0 + db) * nx + x] & sb)) ++db;
     while (dt < W && (mask[(long long)(y0 + W - 1 - dt) * nx + x] & sb)) ++dt;
+    int w = 0;
+    for (int y = y0; y < y0 + W; ++y) w += (mask[(long long)y * nx + x] & sb) ? 0 : 1;
+    area += w;
+    wmin = min(wmin, w);
+    if (x + 1 < x_out) {
+      int dn = 0;
+      while (dn < W && (mask[(long long)(y0 + dn) * nx + x + 1] & sb)) ++dn;
+      steps += abs(dn - db);
+    }
     double col;
     if (db >= W) {
       col = 0.5 * W;
@@ -1037,9 +1051,15 @@ __device__ void capillary_obs(const Src& src, const uint8_t* __restrict__ mask,
   s_min[threadIdx.x] = best;
   s_de[threadIdx.x] = de;
   s_cl[threadIdx.x] = cl;
+  s_area[threadIdx.x] = area;
+  s_wmin[threadIdx.x] = wmin;
+  s_steps[threadIdx.x] = steps;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
+      s_area[threadIdx.x] += s_area[threadIdx.x + s];
+      s_wmin[threadIdx.x] = min(s_wmin[threadIdx.x], s_wmin[threadIdx.x + s]);
+      s_steps[threadIdx.x] += s_steps[threadIdx.x + s];
       s_min[threadIdx.x] = min(s_min[threadIdx.x], s_min[threadIdx.x + s]);
       s_de[threadIdx.x] = fmax(s_de[threadIdx.x], s_de[threadIdx.x + s]);
       const long long o = s_cl[threadIdx.x + s];
@@ -1073,6 +1093,9 @@ __device__ void capillary_obs(const Src& src, const uint8_t* __restrict__ mask,
     out[0] = z;
     out[1] = s_de[0];
     out[2] = (double)s_cl[0];
+    out[3] = (double)s_area[0];
+    out[4] = (double)s_wmin[0];
+    out[5] = (double)s_steps[0];
   }
 }
 
@@ -1092,7 +1115,7 @@ __global__ void __launch_bounds__(256) k_front_batch(const StepArgs* __restrict_
                                                      const long long* __restrict__ stepc,
                                                      int slot, int nslots, int mom,
                                                      double* __restrict__ table) {
-  __shared__ double res[3];
+  __shared__ double res[6];
   const long long step = *stepc;
   const int i = blockIdx.x;
   const StepArgs& a = insts[2 * i + (int)(step & 1)];

@@ -64,7 +64,8 @@ class Obs(C.Structure):
                 ("precipitate", C.c_double), ("solute_removed", C.c_double),
                 ("front_z", C.c_double), ("delta_e", C.c_double),
                 ("closure_step", C.c_int64), ("n_solid", C.c_int64),
-                ("n_events", C.c_int64), ("nonfinite", C.c_int32), ("pad", C.c_int32)]
+                ("n_events", C.c_int64), ("nonfinite", C.c_int32), ("pad", C.c_int32),
+                ("r_min", C.c_double), ("r_ave", C.c_double), ("r_h", C.c_double)]
 
     def as_dict(self) -> dict:
         return {"step": self.step, "mass": (self.mass[0], self.mass[1]),
@@ -73,6 +74,7 @@ class Obs(C.Structure):
                 "solute_removed": self.solute_removed, "front_z": self.front_z,
                 "delta_e": self.delta_e, "closure_step": self.closure_step,
                 "n_solid": self.n_solid, "n_events": self.n_events,
+                "r_min": self.r_min, "r_ave": self.r_ave, "r_h": self.r_h,
                 "nonfinite": self.nonfinite}
 
 

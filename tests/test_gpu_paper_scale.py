@@ -1,0 +1,123 @@
+"""Paper-scale capillaries (section "Results and discussion", Figs. 2-4):
+lengths L = 500 and 1000 lu, heights H = 25 and 100 lu, reaction-rate constant
+k_r = 8e-4 lu/ts, run with and without reaction through the batched HIP path.
+The paper's figures carry no values, so its qualitative statements are the
+checks:
+  * without reaction the front is linear in time (Eq. (1)) and its speed is
+    about halved from L = 500 to L = 1000;
+  * surface growth behind the contact line retards the front, less so for the
+    longer capillary;
+  * narrow capillaries reach pore closure (Delta e close to H/2) sooner and
+    their front stops;
+  * for a given k_r, Delta e(t) hardly depends on the length;
+  * the radii of Fig. 4 satisfy r_min <= r_h <= r_ave <= H and shrink.
+Set-up (readings): the wetting reservoir left of the capillary holds 1.5 times
+the capillary volume so it does not run dry; threshold 1, D = 0.05, C0 = 1,
+30 degree adhesion; 120,000 steps sampled at 50 times."""
+
+import numpy as np
+import pytest
+
+import parity as PT
+from paper_1309_6726_amd import inputs, sweep
+
+pytestmark = pytest.mark.gpu
+
+T = 120_000
+NS = 50
+SHAPES = [(500, 25), (1000, 25), (500, 100), (1000, 100)]
+
+
+def _problem(L, H, k_r, seed):
+    R = int(1.5 * L * H / (H + 12)) + 32
+    return inputs.capillary_problem(R + L + 32, H + 12, H, seed=seed, k_r=k_r, threshold=1.0,
+                                    D=0.05, x_in=R, x_out=R + L)
+
+
+@pytest.fixture(scope="module")
+def runs():
+    from paper_1309_6726_amd import lbm
+    times = sweep.sample_times(T, NS)
+    out = {}
+    for k_r in (8e-4, 0.0):
+        PT.say(f"[paper scale] k_r {k_r}: {len(SHAPES)} capillaries, {T} steps")
+        probs = [_problem(L, H, k_r, i) for i, (L, H) in enumerate(SHAPES)]
+        b = lbm.Batch(probs, graph_chunk=600)
+        rec = {i: [] for i in range(len(probs))}
+        done = 0
+        for t in times:
+            b.step(t - done)
+            done = t
+            for i in range(len(probs)):
+                o = b.observe(i)
+                rec[i].append((t, o["front_z"], o["delta_e"], o["r_min"], o["r_ave"], o["r_h"]))
+        b.close()
+        for i, s in enumerate(SHAPES):
+            out[(s, k_r > 0)] = np.array(rec[i])
+    return np.array(times, dtype=float), out
+
+
+def _fit(t, z):
+    A = np.vstack([t, np.ones_like(t)]).T
+    c, *_ = np.linalg.lstsq(A, z, rcond=None)
+    pred = A @ c
+    r2 = 1.0 - ((z - pred) ** 2).sum() / ((z - z.mean()) ** 2).sum()
+    return c[0], r2
+
+
+def test_washburn_linear_front_and_length_scaling(runs):
+    t, out = runs
+    v = {}
+    for (L, H) in SHAPES:
+        r = out[((L, H), False)]
+        sel = (t >= 0.2 * T) & (r[:, 1] < L - 1)  # before breakthrough
+        assert sel.sum() >= 8
+        v[(L, H)], r2 = _fit(t[sel], r[sel, 1])
+        assert r2 >= 0.999, (L, H, r2)
+    assert 1.7 <= v[(500, 25)] / v[(1000, 25)] <= 2.3
+    assert 1.3 <= v[(500, 100)] / v[(1000, 100)] <= 2.3
+
+
+def test_growth_retards_the_front_less_for_longer_capillaries(runs):
+    t, out = runs
+    for s in SHAPES:
+        zr, z0 = out[(s, True)][:, 1], out[(s, False)][:, 1]
+        assert np.all(zr <= z0 + 0.5), s
+        assert zr[-1] < 0.8 * z0[-1], s
+    for H in (25, 100):
+        for j in (4, 9, 19):  # t = 12k, 24k, 48k
+            short = out[((500, H), True)][j, 1] / out[((500, H), False)][j, 1]
+            long_ = out[((1000, H), True)][j, 1] / out[((1000, H), False)][j, 1]
+            assert long_ >= short - 0.02, (H, j, short, long_)
+
+
+def test_narrow_capillaries_close_sooner_and_stop(runs):
+    t, out = runs
+    for L in (500, 1000):
+        first = {}
+        for H in (25, 100):
+            de = out[((L, H), True)][:, 2]
+            hit = np.nonzero(de >= 0.9 * H / 2)[0]
+            first[H] = t[hit[0]] if len(hit) else np.inf
+        assert first[25] < first[100], (L, first)
+        z = out[((L, 25), True)][:, 1]
+        assert np.argmax(z) < NS // 3 and z[-1] <= z.max(), L
+
+
+def test_growth_kinetics_independent_of_length(runs):
+    t, out = runs
+    for H in (25, 100):
+        a, b = out[((500, H), True)][:, 2], out[((1000, H), True)][:, 2]
+        assert np.abs(a - b).max() <= 0.05 * H, (H, np.abs(a - b).max())
+        assert a[-1] >= 0.4 * H
+
+
+def test_radii_order_and_shrink(runs):
+    t, out = runs
+    for (L, H) in SHAPES:
+        r = out[((L, H), True)]
+        rmin, rave, rh = r[:, 3], r[:, 4], r[:, 5]
+        assert np.all(rmin <= rh + 1e-12) and np.all(rh <= rave + 1e-12) and np.all(rave <= H)
+        assert rave[-1] < rave[0] and rh[-1] < rh[0] and rmin[-1] < rmin[0]
+        r0 = out[((L, H), False)]
+        assert np.all(r0[:, 3:6] == H)

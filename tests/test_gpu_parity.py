@@ -342,3 +342,23 @@ def test_autotune_cache(lbm, tmp_path, monkeypatch):
     assert b.autotune(steps=2)[0] == (tx, sy)
     assert len(path.read_text().splitlines()) == 1
     assert b.tile() == (tx, sy)
+
+
+@pytest.mark.parametrize("scheme", ["moments", "populations"])
+def test_radii_match_oracle(lbm, oracle_mod, scheme):
+    """r_min, r_ave and r_h of Fig. 4 observed on the device equal the
+    oracle's (integer counts on identical solid masks) while the walls grow."""
+    prob = inputs.capillary_problem(300, 40, 20, seed=5, k_r=0.01, threshold=0.4, D=0.05)
+    PT.say(f"[radii] {scheme}: 300x40 reactive capillary, 700 steps")
+    sim = lbm.Sim.from_problem(prob, scheme=scheme)
+    orc = oracle_mod.Oracle.from_problem(prob)
+    go, oo = sim.observe(), orc.observe()
+    assert go["r_min"] == go["r_ave"] == go["r_h"] == 20.0
+    for n in range(100, 701, 100):
+        sim.step(100)
+        orc.step(100)
+        assert PT.event_set(sim.events()) == PT.event_set(orc.events()), n
+        go, oo = sim.observe(), orc.observe()
+        for k in ("r_min", "r_ave", "r_h"):
+            assert go[k] == oo[k], (n, k, go[k], oo[k])
+    assert go["r_h"] <= go["r_ave"] < 20.0 and go["r_min"] < 20.0
