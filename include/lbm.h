@@ -69,6 +69,17 @@ typedef struct {
   double accel[2];   /* uniform body acceleration on both components (tests) */
   int32_t x_in, x_out, y0, W; /* capillary for the observables: section
                         x_in <= x < x_out, channel rows y0..y0+W-1; W = 0: none */
+  /* Variants of the reaction and the solute lattice (section "LB models":
+     precipitation at the surface, an advection-diffusion BGK lattice); all
+     zero gives the plain model above. */
+  double c_eq;       /* saturation concentration: a reacting node precipitates
+                        k_r n_s phi (C - c_eq) when C > c_eq, nothing otherwise;
+                        >= 0 */
+  double c_hold;     /* held source: every fluid node with x < hold_x has its
+                        solute reset each step to the equilibrium at c_hold */
+  int32_t hold_x;    /* 0 = no held source; else 1..nx, needs tau_g > 0 */
+  int32_t solute_q;  /* solute lattice: 0 or 5 = D2Q5 (w0 = 1/3, D = (tau_g-1/2)/3),
+                        4 = D2Q4 (w = 1/4, no rest link, D = (tau_g-1/2)/2) */
 } lbm_params;
 
 /* Observables of the current state (lbm_observe).  Sums are FP64. */

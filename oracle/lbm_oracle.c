@@ -49,6 +49,10 @@ typedef struct {
   double threshold;  /* precipitated mass above which a node turns solid */
   double accel[2];   /* uniform body acceleration (test use) */
   int32_t x_in, x_out, y0, W; /* capillary descriptor, W = 0: none */
+  double c_eq;       /* saturation: precipitation k_r n_s phi (C - c_eq) above it */
+  double c_hold;     /* held concentration of the source region */
+  int32_t hold_x;    /* source region x < hold_x, 0 = none */
+  int32_t solute_q;  /* solute lattice: 0/5 = D2Q5, 4 = D2Q4 */
 } orc_params;
 
 typedef struct {
@@ -113,8 +117,11 @@ void orc_feq(double rho, double ux, double uy, double *out9) {
   }
 }
 
-/* Solute equilibrium on D2Q5, linear in the advecting velocity. */
-static double geq(int k, double C, double ux, double uy) {
+/* Solute equilibrium, linear in the advecting velocity: D2Q5 (sound speed^2
+ * 1/3) or D2Q4 (the four axis links with weight 1/4, sound speed^2 1/2, no
+ * rest link). */
+static double geq(const orc_params *p, int k, double C, double ux, double uy) {
+  if (p->solute_q == 4) return k == 0 ? 0.0 : 0.25 * C * (1.0 + 2.0 * (EX[k] * ux + EY[k] * uy));
   return W5[k] * C * (1.0 + 3.0 * (EX[k] * ux + EY[k] * uy));
 }
 
@@ -125,6 +132,10 @@ int orc_check_params(const orc_params *p) {
   if (!(p->tau_g == 0.0 || p->tau_g > 0.5)) return 0;
   if (!(p->k_r >= 0.0) || 4.0 * p->k_r > 1.0) return 0;
   if (!(p->threshold > 0.0)) return 0;
+  if (!(p->c_eq >= 0.0) || !isfinite(p->c_eq)) return 0;
+  if (!(p->c_hold >= 0.0) || !isfinite(p->c_hold)) return 0;
+  if (p->hold_x < 0 || p->hold_x > p->nx || (p->hold_x > 0 && p->tau_g == 0.0)) return 0;
+  if (p->solute_q != 0 && p->solute_q != 4 && p->solute_q != 5) return 0;
   if (p->W < 0) return 0;
   if (p->W > 0) {
     if (p->x_in < 0 || p->x_out > p->nx || p->x_in + 2 > p->x_out) return 0;
@@ -190,7 +201,7 @@ orc_sim *orc_create(const orc_params *p, const uint8_t *solid, const double *rho
       F(sim, 1, i, k) = W9[i] * rho2[k];
     }
     if (conc)
-      for (int q = 0; q < 5; q++) Gq(sim, q, k) = W5[q] * conc[k];
+      for (int q = 0; q < 5; q++) Gq(sim, q, k) = geq(p, q, conc[k], 0.0, 0.0);
   }
   return sim;
 }
@@ -335,10 +346,12 @@ static void step_once(orc_sim *sim) {
     for (long k = 0; k < N; k++) {
       if (sim->s[k]) continue;
       for (int q = 0; q < 5; q++)
-        GS(sim, q, k) = Gq(sim, q, k) - (Gq(sim, q, k) - geq(q, sim->C[k], sim->ux[k], sim->uy[k])) / p->tau_g;
+        GS(sim, q, k) = Gq(sim, q, k) - (Gq(sim, q, k) - geq(p, q, sim->C[k], sim->ux[k], sim->uy[k])) / p->tau_g;
     }
     /* S6 surface reaction at fluid nodes with n_s >= 1 solid axis neighbours:
-     * r = k_r n_s phi, m += r C, solute populations scaled by (1 - r). */
+     * r = k_r n_s phi, m += r C, solute populations scaled by (1 - r).  With a
+     * saturation concentration c_eq > 0 only the excess precipitates:
+     * m += r (C - c_eq) when C > c_eq, and the solute keeps C - r (C - c_eq). */
     if (p->k_r > 0) {
 #pragma omp parallel for schedule(static)
       for (long y = 0; y < p->ny; y++) {
@@ -349,10 +362,30 @@ static void step_once(orc_sim *sim) {
           if (ns == 0) continue;
           double phi = sim->rho[k] / (sim->rho[k] + sim->rho[N + k]);
           double r = p->k_r * ns * phi;
-          sim->m[k] += r * sim->C[k];
-          for (int q = 0; q < 5; q++) GS(sim, q, k) *= (1.0 - r);
+          if (p->c_eq > 0) {
+            double excess = sim->C[k] > p->c_eq ? sim->C[k] - p->c_eq : 0.0;
+            double dm = r * excess;
+            sim->m[k] += dm;
+            if (dm > 0)
+              for (int q = 0; q < 5; q++) GS(sim, q, k) *= (1.0 - dm / sim->C[k]);
+          } else {
+            sim->m[k] += r * sim->C[k];
+            for (int q = 0; q < 5; q++) GS(sim, q, k) *= (1.0 - r);
+          }
         }
       }
+    }
+    /* held source: the post-collision solute of every fluid node with
+     * x < hold_x is the equilibrium at c_hold (a reservoir kept at fixed
+     * concentration) */
+    if (p->hold_x > 0) {
+#pragma omp parallel for schedule(static)
+      for (long y = 0; y < p->ny; y++)
+        for (long x = 0; x < p->hold_x; x++) {
+          long k = y * p->nx + x;
+          if (sim->s[k]) continue;
+          for (int q = 0; q < 5; q++) GS(sim, q, k) = geq(p, q, p->c_hold, sim->ux[k], sim->uy[k]);
+        }
     }
   }
 

@@ -101,6 +101,13 @@ lbm_status check_params(const lbm_params* p) {
   if (!std::isfinite(p->G) || !std::isfinite(p->G_ads[0]) || !std::isfinite(p->G_ads[1]) ||
       !std::isfinite(p->accel[0]) || !std::isfinite(p->accel[1]))
     return fail(LBM_EINVAL, "non-finite force parameter");
+  if (!(p->c_eq >= 0.0) || !std::isfinite(p->c_eq)) return fail(LBM_EINVAL, "c_eq must be finite and >= 0");
+  if (!(p->c_hold >= 0.0) || !std::isfinite(p->c_hold))
+    return fail(LBM_EINVAL, "c_hold must be finite and >= 0");
+  if (p->hold_x < 0 || p->hold_x > p->nx) return fail(LBM_EINVAL, "hold_x must be in [0, nx]");
+  if (p->hold_x > 0 && p->tau_g == 0.0) return fail(LBM_EINVAL, "a held source needs the solute lattice");
+  if (p->solute_q != 0 && p->solute_q != 4 && p->solute_q != 5)
+    return fail(LBM_EINVAL, "solute_q must be 0, 4 or 5");
   if (p->W < 0) return fail(LBM_EINVAL, "W must be >= 0");
   if (p->W > 0) {
     if (p->x_in < 0 || p->x_out > p->nx || p->x_in + 2 > p->x_out)
@@ -205,6 +212,10 @@ lbm_status queue_steps(lbm_sim* s, long long n) {
   a.omega_g = s->L.solute ? (float)(1.0 / p.tau_g) : 0.0f;
   a.k_r = p.k_r;
   a.threshold = p.threshold;
+  a.c_eq = p.c_eq;
+  a.c_hold = p.c_hold;
+  a.hold_x = p.hold_x;
+  a.q4 = p.solute_q == 4;
   for (long long t = 0; t < n; ++t) {
     const int kind = !moments ? KIND_POP : (s->mom ? KIND_MM : KIND_PM);
     a.tx_owned = kind == KIND_MM ? 60 : s->tx - 2;  // the moment step: 64-lane tiles
@@ -348,7 +359,8 @@ lbm_status lbm_init(const lbm_params* p, const uint8_t* solid, const double* rho
   CK(hipMemsetAsync(s->evc(), 0, sizeof(unsigned long long), hs));
   CK(launch_init((const double*)stage, (const double*)(stage + N * sizeof(double)),
                  solute ? (const double*)(stage + 2 * N * sizeof(double)) : nullptr, s->mask(),
-                 s->f(0), s->g(0), s->m(), s->sstep(), s->drop(), N, L.P, solute, L.react, hs));
+                 s->f(0), s->g(0), s->m(), s->sstep(), s->drop(), N, L.P, solute, L.react,
+                 p->solute_q == 4, hs));
   CK(hipStreamSynchronize(hs));
 #undef CK
   *out = s;
@@ -514,6 +526,12 @@ lbm_status lbm_load(lbm_sim* s, const void* blob, size_t n) {
   const unsigned allowed = 1u | pending_bit(step - 1) | pending_bit(step - 2);
   for (long long i = 0; i < N; ++i)
     if ((unsigned)(uint8_t)mb[i] & ~allowed) return fail(LBM_EINVAL, "bad mask byte at node %lld", i);
+  if (s->L.solute && s->p.solute_q == 4) {
+    // the D2Q4 solute lattice has no rest link: its plane must be empty
+    const float* g0 = (const float*)(b + 18 * N * 4);
+    for (long long i = 0; i < N; ++i)
+      if (g0[i] != 0.0f) return fail(LBM_EINVAL, "D2Q4 checkpoint with a rest solute population at node %lld", i);
+  }
   lbm_status st;
   if ((st = copy_planes_h2d((char*)s->f(0), b, 18, N, P, 4, s->stream)) != LBM_OK) return st;
   b += 18 * N * 4;
@@ -748,6 +766,11 @@ int tiles_for(const lbm_params& p, int tx, int sy) {
 }
 
 bool batch_moments(const lbm_batch* b) { return use_moments(b->scheme, b->p[0]); }
+bool batch_variants(const lbm_batch* b) {
+  for (const lbm_params& p : b->p)
+    if (p.c_eq > 0.0 || p.hold_x > 0 || p.solute_q == 4) return true;
+  return false;
+}
 int batch_tx(const lbm_batch* b) { return batch_moments(b) ? 64 : b->tx; }
 
 lbm_status batch_layout(int n, const lbm_params* p, int nslots, BatchLayout* B) {
@@ -830,6 +853,10 @@ StepArgs instance_args(const lbm_batch* b, int i, int parity) {
   a.omega_g = L.solute ? (float)(1.0 / p.tau_g) : 0.0f;
   a.k_r = p.k_r;
   a.threshold = p.threshold;
+  a.c_eq = p.c_eq;
+  a.c_hold = p.c_hold;
+  a.hold_x = p.hold_x;
+  a.q4 = p.solute_q == 4;
   return a;
 }
 
@@ -883,7 +910,7 @@ lbm_status batch_reset(lbm_batch* b) {
                          L.react ? (double*)(w + L.m) : nullptr,
                          L.react ? (int32_t*)(w + L.sstep) : nullptr,
                          L.react ? (float*)(w + L.drop) : nullptr, L.N, L.P, L.solute, L.react,
-                         b->stream));
+                         b->p[i].solute_q == 4, b->stream));
   }
   HIPCHECK(hipMemsetAsync(b->d_step, 0, sizeof(long long), b->stream));
   HIPCHECK(hipStreamSynchronize(b->stream));
@@ -900,7 +927,8 @@ lbm_status batch_launch(lbm_batch* b, long long nsteps) {
   for (long long t = 0; t < nsteps; ++t) {
     const int kind = batch_kind(b);
     hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step, batch_tx(b),
-                                     b->solute, b->react, b->arith64, kind, b->stream);
+                                     b->solute, b->react, batch_variants(b), b->arith64, kind,
+                                     b->stream);
     if (e != hipSuccess) {
       b->poisoned = true;
       return fail(LBM_EDEVICE, "batch step launch: %s", hipGetErrorString(e));
@@ -1049,8 +1077,8 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
       HIPCHECK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       for (int t = 0; t < b->graph_chunk; ++t) {
         hipError_t e = launch_step_batch(b->d_insts, b->d_tiles, b->ntiles, b->d_step,
-                                         batch_tx(b), b->solute, b->react, b->arith64,
-                                         batch_kind(b), b->cap_stream);
+                                         batch_tx(b), b->solute, b->react, batch_variants(b),
+                                         b->arith64, batch_kind(b), b->cap_stream);
         if (e != hipSuccess) {
           (void)hipStreamEndCapture(b->cap_stream, &g);
           if (g) (void)hipGraphDestroy(g);

@@ -41,6 +41,10 @@ struct StepArgs {
   float G, Gads1, Gads2, ax, ay;
   float omega_g;      // 1/tau_g
   double k_r, threshold;
+  double c_eq;        // saturation concentration of the reaction (0: plain first order)
+  double c_hold;      // held concentration of the source region x < hold_x
+  int hold_x;         // 0: no held source
+  int q4;             // 1: D2Q4 solute lattice, 0: D2Q5
 };
 
 // Growth marks rotate over three pending bits: step n marks a node with
@@ -63,9 +67,10 @@ enum StepKind { KIND_POP = 0, KIND_PM = 1, KIND_MM = 2 };
 lbm_status fail(lbm_status s, const char* fmt, ...);
 
 hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, hipStream_t st);
+// var: some instance uses a reaction or solute-lattice variant
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
-                             const long long* stepc, int tx, int solute, int react, int arith64,
-                             int kind, hipStream_t st);
+                             const long long* stepc, int tx, int solute, int react, int var,
+                             int arith64, int kind, hipStream_t st);
 hipError_t launch_front_batch(const StepArgs* insts, const int4* capi, const long long* stepc,
                               int n, int slot, int nslots, int mom, double* table, hipStream_t st);
 // Populations of state n rebuilt from stored moments (zero at nodes solid in
@@ -75,7 +80,7 @@ hipError_t launch_unpack(const float* M, const uint8_t* mask, int nx, int ny, lo
 int host_xcd_tile(int b, int T);
 hipError_t launch_init(const double* r1, const double* r2, const double* c, const uint8_t* mask,
                        float* f, float* g, double* m, int32_t* sstep, float* drop, long long N,
-                       long long P, int solute, int react, hipStream_t st);
+                       long long P, int solute, int react, int q4, hipStream_t st);
 // Observers of state n.  f holds populations (mom = 0) or the moments of the
 // last step (mom = 1); p1, p2 are pending(n-1), pending(n-2).
 hipError_t launch_observe(const float* f, const float* g, const uint8_t* mask, const double* m,

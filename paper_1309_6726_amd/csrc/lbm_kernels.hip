@@ -137,35 +137,49 @@ __device__ __forceinline__ void sc_velocities(R tau, R rho1, R rho2, R j1x, R j1
   uy = (j1y + j2y + R(0.5) * (F1y + F2y)) * irt;
 }
 
-// Solute collision (D2Q5 BGK advected by u), first-order precipitation at a
-// node with ns > 0 solid axis neighbours (rate k_r ns phi, phi the wetting
-// fraction), threshold test, and push of the solute populations (bounce-back
-// at solid axis neighbours).  sf: solid flags of the axis neighbours 1..4.
-template <bool REACT, typename R>
+// Solute collision (BGK on D2Q5, or on D2Q4 with weights 1/4 and no rest
+// link, advected by u), first-order precipitation at a node with ns > 0 solid
+// axis neighbours (rate k_r ns phi, phi the wetting fraction; with a
+// saturation concentration c_eq > 0 only the excess C - c_eq precipitates),
+// the held source (post-collision solute of a node with x < hold_x set to the
+// equilibrium at c_hold), threshold test, and push of the solute populations
+// (bounce-back at solid axis neighbours).  sf: solid flags of the axis
+// neighbours 1..4.
+template <bool REACT, bool VAR, typename R>
 __device__ __forceinline__ void solute_step(const StepArgs& a, const float* g, R ux, R uy,
                                             R rho1, R rho2, const float* sf, double m_cur,
                                             unsigned P, unsigned idx, unsigned iE, unsigned iN,
                                             unsigned iW, unsigned iS, int xc, int y, bool& ev,
                                             int& evx, int& evy) {
-  const R W5A = R(1) / R(6);
+  // VAR = false: the plain model (D2Q5, c_eq = 0, no held source)
+  const bool q4 = VAR && a.q4 != 0;
+  const R WQ = q4 ? R(0.25) : R(1) / R(6), CQ = q4 ? R(2) : R(3);
   const R C = (((R)g[0] + (R)g[1]) + ((R)g[2] + (R)g[3])) + (R)g[4];
   const R og = (R)a.omega_g;
   R gs[5];
-  gs[1] = (R)g[1] + og * (W5A * C * (R(1) + R(3) * ux) - (R)g[1]);
-  gs[2] = (R)g[2] + og * (W5A * C * (R(1) + R(3) * uy) - (R)g[2]);
-  gs[3] = (R)g[3] + og * (W5A * C * (R(1) - R(3) * ux) - (R)g[3]);
-  gs[4] = (R)g[4] + og * (W5A * C * (R(1) - R(3) * uy) - (R)g[4]);
-  gs[0] = C - ((gs[1] + gs[2]) + (gs[3] + gs[4]));
+  gs[1] = (R)g[1] + og * (WQ * C * (R(1) + CQ * ux) - (R)g[1]);
+  gs[2] = (R)g[2] + og * (WQ * C * (R(1) + CQ * uy) - (R)g[2]);
+  gs[3] = (R)g[3] + og * (WQ * C * (R(1) - CQ * ux) - (R)g[3]);
+  gs[4] = (R)g[4] + og * (WQ * C * (R(1) - CQ * uy) - (R)g[4]);
+  gs[0] = q4 ? R(0) : C - ((gs[1] + gs[2]) + (gs[3] + gs[4]));
   if (REACT) {
     const int ns = (int)sf[1] + (int)sf[2] + (int)sf[3] + (int)sf[4];
     if (ns > 0) {
       const double phi = (double)rho1 / ((double)rho1 + (double)rho2);
       const double rr = a.k_r * (double)ns * phi;
-      const double mm = m_cur + rr * (double)C;
+      double dm, keep;
+      if (VAR && a.c_eq > 0.0) {
+        const double excess = (double)C > a.c_eq ? (double)C - a.c_eq : 0.0;
+        dm = rr * excess;
+        keep = dm > 0.0 ? 1.0 - dm / (double)C : 1.0;
+      } else {
+        dm = rr * (double)C;
+        keep = 1.0 - rr;
+      }
+      const double mm = m_cur + dm;
       a.m[idx] = mm;
-      const R keep = (R)(1.0 - rr);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) gs[q] *= keep;
+      for (int q = 0; q < 5; ++q) gs[q] *= (R)keep;
       if (mm > a.threshold) {
         a.mask[idx] = (uint8_t)a.bit_cur;
         a.sstep[idx] = (int32_t)(a.step + 1);
@@ -174,6 +188,14 @@ __device__ __forceinline__ void solute_step(const StepArgs& a, const float* g, R
         evy = y;
       }
     }
+  }
+  if (VAR && xc < a.hold_x) {
+    const R Ch = (R)a.c_hold;
+    gs[1] = WQ * Ch * (R(1) + CQ * ux);
+    gs[2] = WQ * Ch * (R(1) + CQ * uy);
+    gs[3] = WQ * Ch * (R(1) - CQ * ux);
+    gs[4] = WQ * Ch * (R(1) - CQ * uy);
+    gs[0] = q4 ? R(0) : (R(1) - R(4) * WQ) * Ch;
   }
   float* __restrict__ go = a.gout;
   go[idx] = (float)gs[0];
@@ -258,7 +280,7 @@ __device__ __forceinline__ void moments9(const R* f, R& rho, R& jx, R& jy) {
 // memory round trip plus ~1 us of VALU work per wave, so resident waves are
 // what hides the memory latency.  OUTM (tau = 1 only): store the moments
 // (rho_s, v_s) of the collided node instead of pushing populations.
-template <bool SOLUTE, bool REACT, typename R, bool OUTM>
+template <bool SOLUTE, bool REACT, bool VAR, typename R, bool OUTM>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
   const int TX = blockDim.x;
   R* s_r1 = (R*)lds_raw;                 // [4][TX] density of component 1 (0 at solid)
@@ -423,7 +445,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
           collide_push(f + 9, 9u, rho2, v2x, v2y);
         }
         if (SOLUTE)
-          solute_step<REACT, R>(a, g, ux, uy, rho1, rho2, sf, m_cur, P, idx, iE, iN, iW, iS, xc, y,
+          solute_step<REACT, VAR, R>(a, g, ux, uy, rho1, rho2, sf, m_cur, P, idx, iE, iN, iW, iS, xc, y,
                                 ev, evx, evy);
       }
     }
@@ -493,7 +515,7 @@ __device__ __forceinline__ R feq_m(R wr, R c, R eu) {
 // rows ahead into a register, so one iteration's arithmetic covers the next
 // iteration's memory latency.  The summation order of every node is fixed,
 // so results do not depend on the tile shape.
-template <bool SOLUTE, bool REACT, typename R>
+template <bool SOLUTE, bool REACT, bool VAR, typename R>
 __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) {
   // prefetch slots per buffer: 0..5 moments, 6..10 solute, 11..12 precipitate
   __shared__ float pf[2][13][64];
@@ -729,7 +751,7 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
           const double mC =
               cur_p ? __hiloint2double(__float_as_int(pf[buf][12][t]), __float_as_int(pf[buf][11][t]))
                     : 0.0;
-          solute_step<REACT, R>(a, gv, ux, uy, rC[0], rC[3], sf, mC, P, idx, iE, iN, iW, iS, xc,
+          solute_step<REACT, VAR, R>(a, gv, ux, uy, rC[0], rC[3], sf, mC, P, idx, iE, iN, iW, iS, xc,
                                 y, ev, evx, evy);
         }
       }
@@ -763,22 +785,22 @@ __host__ __device__ inline int xcd_tile(int b, int T) {
   return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
-template <bool SOLUTE, bool REACT, typename R, int KIND>
+template <bool SOLUTE, bool REACT, bool VAR, typename R, int KIND>
 __device__ __forceinline__ void run_tile(const StepArgs& a, int strip, int seg, char* lds_raw) {
   if (KIND == KIND_MM)
-    mom_wave<SOLUTE, REACT, R>(a, strip, seg);
+    mom_wave<SOLUTE, REACT, VAR, R>(a, strip, seg);
   else
-    step_tile<SOLUTE, REACT, R, KIND == KIND_PM>(a, strip, seg, lds_raw);
+    step_tile<SOLUTE, REACT, VAR, R, KIND == KIND_PM>(a, strip, seg, lds_raw);
 }
 
-template <bool SOLUTE, bool REACT, typename R, int KIND>
+template <bool SOLUTE, bool REACT, bool VAR, typename R, int KIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_step(const StepArgs a) {
   extern __shared__ char lds_raw[];
   const int T = a.nstrips * a.nsegs;
   const int tile = a.remap ? xcd_tile(blockIdx.x, T) : (int)blockIdx.x;
   const int strip = tile / a.nsegs;
-  run_tile<SOLUTE, REACT, R, KIND>(a, strip, tile - strip * a.nsegs, lds_raw);
+  run_tile<SOLUTE, REACT, VAR, R, KIND>(a, strip, tile - strip * a.nsegs, lds_raw);
 }
 
 // Batched step: one launch advances every instance of a batch by one step.
@@ -786,7 +808,7 @@ k_step(const StepArgs a) {
 // list per XCD); the instance's arguments for the current parity come from
 // device memory, and the step index from the device counter, so a sequence of
 // launches can be captured once in a graph and replayed.
-template <bool SOLUTE, bool REACT, typename R, int KIND>
+template <bool SOLUTE, bool REACT, bool VAR, typename R, int KIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_step_batch(const StepArgs* __restrict__ insts, const int4* __restrict__ tiles,
              const long long* __restrict__ stepc) {
@@ -798,7 +820,7 @@ k_step_batch(const StepArgs* __restrict__ insts, const int4* __restrict__ tiles,
   a.bit_p1 = pending_bit(step - 1);
   a.bit_p2 = pending_bit(step - 2);
   a.bit_cur = pending_bit(step);
-  run_tile<SOLUTE, REACT, R, KIND>(a, e.y, e.z, lds_raw);
+  run_tile<SOLUTE, REACT, VAR, R, KIND>(a, e.y, e.z, lds_raw);
 }
 
 // Advances the device step counter (a vector atomic, one lane).
@@ -811,10 +833,11 @@ __global__ void k_init(const double* __restrict__ rho1, const double* __restrict
                        const double* __restrict__ conc, const uint8_t* __restrict__ mask,
                        float* __restrict__ f, float* __restrict__ g, double* __restrict__ m,
                        int32_t* __restrict__ sstep, float* __restrict__ drop, long long N,
-                       long long P, int solute, int react) {
+                       long long P, int solute, int react, int q4) {
   const float w9[9] = {4.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f, 1.0f / 9.0f,
                        1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f, 1.0f / 36.0f};
-  const float w5[5] = {1.0f / 3.0f, 1.0f / 6.0f, 1.0f / 6.0f, 1.0f / 6.0f, 1.0f / 6.0f};
+  const float w5[5] = {q4 ? 0.0f : 1.0f / 3.0f, q4 ? 0.25f : 1.0f / 6.0f, q4 ? 0.25f : 1.0f / 6.0f,
+                       q4 ? 0.25f : 1.0f / 6.0f, q4 ? 0.25f : 1.0f / 6.0f};
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     const bool s = mask[i] != 0;
@@ -1212,14 +1235,23 @@ size_t step_lds_bytes(int kind, int tx, int arith64) {
   return (size_t)4 * tx * (2 * r + sizeof(float));
 }
 
+// Runs that use a reaction or solute-lattice variant (saturation, held
+// source, D2Q4) take their own instantiation, so the plain model keeps its
+// instruction stream.
+inline bool uses_variants(const StepArgs& a) { return a.c_eq > 0.0 || a.hold_x > 0 || a.q4; }
+
 template <typename R, int KIND>
 void launch_step_t(const StepArgs& a, int T, int tx, size_t lds, hipStream_t st) {
-  if (a.solute && a.react)
-    hipLaunchKernelGGL((k_step<true, true, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+  if (a.solute && a.react && uses_variants(a))
+    hipLaunchKernelGGL((k_step<true, true, true, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+  else if (a.solute && a.react)
+    hipLaunchKernelGGL((k_step<true, true, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+  else if (a.solute && uses_variants(a))
+    hipLaunchKernelGGL((k_step<true, false, true, R, KIND>), dim3(T), dim3(tx), lds, st, a);
   else if (a.solute)
-    hipLaunchKernelGGL((k_step<true, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+    hipLaunchKernelGGL((k_step<true, false, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
   else
-    hipLaunchKernelGGL((k_step<false, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+    hipLaunchKernelGGL((k_step<false, false, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
 }
 
 hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, hipStream_t st) {
@@ -1240,28 +1272,32 @@ hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, hipStre
 
 template <typename R, int KIND>
 void launch_batch_t(const StepArgs* insts, const int4* tiles, int ntiles, const long long* stepc,
-                    int tx, int solute, int react, size_t lds, hipStream_t st) {
-  if (solute && react)
-    hipLaunchKernelGGL((k_step_batch<true, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+                    int tx, int solute, int react, int var, size_t lds, hipStream_t st) {
+  if (solute && react && var)
+    hipLaunchKernelGGL((k_step_batch<true, true, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+  else if (solute && react)
+    hipLaunchKernelGGL((k_step_batch<true, true, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+  else if (solute && var)
+    hipLaunchKernelGGL((k_step_batch<true, false, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
   else if (solute)
-    hipLaunchKernelGGL((k_step_batch<true, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    hipLaunchKernelGGL((k_step_batch<true, false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
   else
-    hipLaunchKernelGGL((k_step_batch<false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    hipLaunchKernelGGL((k_step_batch<false, false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
 }
 
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
-                             const long long* stepc, int tx, int solute, int react, int arith64,
-                             int kind, hipStream_t st) {
+                             const long long* stepc, int tx, int solute, int react, int var,
+                             int arith64, int kind, hipStream_t st) {
   if (kind == KIND_MM) tx = 64;
   const size_t lds = step_lds_bytes(kind, tx, arith64);
   if (arith64) {
-    if (kind == KIND_MM) launch_batch_t<double, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
-    else if (kind == KIND_PM) launch_batch_t<double, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
-    else launch_batch_t<double, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
+    if (kind == KIND_MM) launch_batch_t<double, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
+    else if (kind == KIND_PM) launch_batch_t<double, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
+    else launch_batch_t<double, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
   } else {
-    if (kind == KIND_MM) launch_batch_t<float, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
-    else if (kind == KIND_PM) launch_batch_t<float, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
-    else launch_batch_t<float, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, lds, st);
+    if (kind == KIND_MM) launch_batch_t<float, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
+    else if (kind == KIND_PM) launch_batch_t<float, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
+    else launch_batch_t<float, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
   }
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, (long long*)stepc);
   return hipGetLastError();
@@ -1280,9 +1316,9 @@ static int grid_for(long long N) { return (int)((N + 255) / 256 < 8192 ? (N + 25
 
 hipError_t launch_init(const double* r1, const double* r2, const double* c, const uint8_t* mask,
                        float* f, float* g, double* m, int32_t* sstep, float* drop, long long N,
-                       long long P, int solute, int react, hipStream_t st) {
+                       long long P, int solute, int react, int q4, hipStream_t st) {
   hipLaunchKernelGGL(k_init, dim3(grid_for(N)), dim3(256), 0, st, r1, r2, c, mask, f, g, m, sstep,
-                     drop, N, P, solute, react);
+                     drop, N, P, solute, react, q4);
   return hipGetLastError();
 }
 

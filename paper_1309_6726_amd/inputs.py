@@ -118,6 +118,10 @@ class Params:
     x_out: int = 0
     y0: int = 0
     W: int = 0                  # 0: no capillary observables
+    c_eq: float = 0.0           # saturation concentration of the reaction (0: plain first order)
+    c_hold: float = 0.0         # held solute concentration of the source region
+    hold_x: int = 0             # source region x < hold_x (0: no source)
+    solute_q: int = 0           # solute lattice: 0/5 D2Q5, 4 D2Q4
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

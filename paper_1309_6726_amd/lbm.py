@@ -46,7 +46,8 @@ class Params(C.Structure):
                 ("G", C.c_double), ("G_ads", C.c_double * 2), ("tau_g", C.c_double),
                 ("k_r", C.c_double), ("threshold", C.c_double), ("accel", C.c_double * 2),
                 ("x_in", C.c_int32), ("x_out", C.c_int32), ("y0", C.c_int32),
-                ("W", C.c_int32)]
+                ("W", C.c_int32), ("c_eq", C.c_double), ("c_hold", C.c_double),
+                ("hold_x", C.c_int32), ("solute_q", C.c_int32)]
 
     @classmethod
     def of(cls, p) -> "Params":
@@ -55,7 +56,9 @@ class Params(C.Structure):
                    (C.c_double * 2)(float(p.G_ads1), float(p.G_ads2)), float(p.tau_g),
                    float(p.k_r), float(p.threshold),
                    (C.c_double * 2)(float(p.accel_x), float(p.accel_y)),
-                   int(p.x_in), int(p.x_out), int(p.y0), int(p.W))
+                   int(p.x_in), int(p.x_out), int(p.y0), int(p.W),
+                   float(getattr(p, "c_eq", 0.0)), float(getattr(p, "c_hold", 0.0)),
+                   int(getattr(p, "hold_x", 0)), int(getattr(p, "solute_q", 0)))
 
 
 class Obs(C.Structure):

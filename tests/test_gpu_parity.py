@@ -80,25 +80,17 @@ def _random_state(nx, ny, seed, solid_frac=0.25, m_hi=0.5):
     return solid, f, g, m
 
 
-@pytest.mark.parametrize("tau", [0.9, 1.0])
-@pytest.mark.parametrize("nx,ny,tile", [(8, 8, (64, 4)), (37, 23, (64, 8)), (300, 19, (128, 16)),
-                                        (509, 40, (256, 32))])
-def test_random_state_all_terms(lbm, oracle_mod, nx, ny, tile, tau):
-    """Random non-equilibrium two-phase states with random walls and
-    precipitate, every term on (forces, adhesion, body force, solute,
-    reaction, growth), ragged tiles: 30 steps, fields and events.  At
-    tau = 1 the first step reads the loaded populations and stores moments;
-    the later steps rebuild the populations from moments (growth bookings
-    and mask folds included)."""
-    PT.say(f"[random state] {nx}x{ny} tile {tile} tau {tau}")
+def _random_state_run(lbm, oracle_mod, nx, ny, tile, tau, **variant):
     solid, f, g, m = _random_state(nx, ny, seed=nx * 1000 + ny)
+    if variant.get("solute_q") == 4:
+        g[0] = 0.0  # D2Q4: no rest link
     # prime a few wall-adjacent nodes to grow within the run
     walls = sum(np.roll(solid, s, axis=a) for s in (1, -1) for a in (0, 1))
     cand = np.argwhere((solid == 0) & (walls > 0))
     for k in range(min(5, len(cand))):
         m[tuple(cand[k * len(cand) // 5])] = 0.9985 + 0.0001 * k
     p = inputs.Params(nx=nx, ny=ny, tau=tau, G=1.6, G_ads1=-0.33, G_ads2=0.33, tau_g=0.65,
-                      k_r=0.01, threshold=1.0, accel_x=2e-5, accel_y=-1e-5)
+                      k_r=0.01, threshold=1.0, accel_x=2e-5, accel_y=-1e-5, **variant)
     sim = lbm.Sim(p, solid, np.where(solid, 0.0, 1.0), np.where(solid, 0.0, 1.0),
                   np.zeros((ny, nx)), tile=tile)
     sim.load_state(f, solid, g, m)
@@ -116,6 +108,49 @@ def test_random_state_all_terms(lbm, oracle_mod, nx, ny, tile, tau):
     for s in range(2):
         assert abs(go["mass_removed"][s] - oo["mass_removed"][s]) <= 1e-5 * max(1.0, oo["mass_removed"][s])
     assert go["n_solid"] == oo["n_solid"] and go["n_events"] == oo["n_events"]
+
+
+@pytest.mark.parametrize("tau", [0.9, 1.0])
+@pytest.mark.parametrize("nx,ny,tile", [(8, 8, (64, 4)), (37, 23, (64, 8)), (300, 19, (128, 16)),
+                                        (509, 40, (256, 32))])
+def test_random_state_all_terms(lbm, oracle_mod, nx, ny, tile, tau):
+    """Random non-equilibrium two-phase states with random walls and
+    precipitate, every term on (forces, adhesion, body force, solute,
+    reaction, growth), ragged tiles: 30 steps, fields and events.  At
+    tau = 1 the first step reads the loaded populations and stores moments;
+    the later steps rebuild the populations from moments (growth bookings
+    and mask folds included)."""
+    PT.say(f"[random state] {nx}x{ny} tile {tile} tau {tau}")
+    _random_state_run(lbm, oracle_mod, nx, ny, tile, tau)
+
+
+VARIANTS = {"saturation": dict(c_eq=0.3), "held source": dict(hold_x=7, c_hold=0.7),
+            "d2q4": dict(solute_q=4), "all": dict(c_eq=0.2, hold_x=5, c_hold=0.9, solute_q=4)}
+
+
+@pytest.mark.parametrize("tau", [0.9, 1.0])
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("nx,ny,tile", [(37, 23, (64, 8)), (300, 19, (128, 16))])
+def test_reaction_variants(lbm, oracle_mod, nx, ny, tile, variant, tau):
+    """Saturation concentration, held source and the D2Q4 solute lattice on
+    random states (every other term on), against the oracle, both schemes."""
+    PT.say(f"[variant {variant}] {nx}x{ny} tile {tile} tau {tau}")
+    _random_state_run(lbm, oracle_mod, nx, ny, tile, tau, **VARIANTS[variant])
+
+
+def test_d2q4_checkpoint_rejects_rest_population(lbm):
+    p = inputs.Params(nx=16, ny=8, tau_g=0.7, solute_q=4)
+    solid = np.zeros((8, 16), np.uint8)
+    sim = lbm.Sim(p, solid, np.ones((8, 16)), np.zeros((8, 16)), np.ones((8, 16)))
+    f = np.zeros((18, 8, 16))
+    f[0] = 1.0
+    g = np.zeros((5, 8, 16))
+    g[1:] = 0.25
+    sim.load_state(f, solid, g)
+    g[0, 3, 3] = 0.1
+    with pytest.raises(lbm.LbmError) as e:
+        sim.load_state(f, solid, g)
+    assert e.value.status == lbm.LBM_EINVAL
 
 
 def test_config1_events_exact_windows(lbm, oracle_mod):
