@@ -148,27 +148,27 @@ def surrogate_section(args, torch, dev, sweep_out):
     rows, x, fr, cl, gen_s = S.generate(1, args.surr_train, T, device=dev)
     rows_t, x_t, fr_t, cl_t, gen_t = S.generate(2, args.surr_test, T, device=dev)
     y = S.make_targets(x, fr, cl, T)
-    net = S.Surrogate(max_batch=256, max_data=args.surr_train, device=dev)
+    ens = S.Ensemble(args.surr_members, max_batch=256, max_data=args.surr_train, device=dev)
     t0 = time.perf_counter()
-    # the confidence gate is chosen on runs the network has not seen: train on
-    # all but the last 1/8 of the training runs, pick the gate on that 1/8,
-    # then train again on every training run
+    # the confidence gates are chosen on runs the networks have not seen: the
+    # ensemble is trained on all but the last 1/8 of the training runs and its
+    # gates are picked on that 1/8; the same ensemble then answers
     nv = len(rows) // 8
-    S.train(net, x[:-nv], y[:-nv], epochs=args.surr_epochs, lr=2e-3, log_every=args.surr_epochs)
-    gate = S.choose_gate(net, x[-nv:], fr[-nv:], T)
-    hist = S.train(net, x, y, epochs=args.surr_epochs, lr=2e-3, log_every=args.surr_epochs)
+    hist = ens.train(x[:-nv], y[:-nv], epochs=args.surr_epochs, lr=2e-3,
+                     log_every=args.surr_epochs)
+    gates = S.choose_gates(ens, x[-nv:], fr[-nv:], T, target=0.005)
     train_s = time.perf_counter() - t0
-    # raw network on the held-out runs
-    yp = net.predict(x_t).astype(np.float64)
-    f_raw, c_raw = S.decode(x_t, yp, T)
+    # raw networks on the held-out runs: one member, and the ensemble mean
+    e_one = S.front_error(S.decode(x_t, ens.members[0].predict(x_t).astype(np.float64), T)[0], fr_t)
+    f_raw, c_raw = S.decode(x_t, ens.predict(x_t), T)
     e_raw = S.front_error(f_raw, fr_t)
-    # gated answers (network where confident, LB elsewhere)
-    f_g, c_g, use, net_s, lb_s = S.answer(net, rows_t, T, gate, device=dev)
+    # gated answers (ensemble where confident, LB elsewhere)
+    f_g, c_g, use, net_s, lb_s = S.answer(ens, rows_t, T, gates, device=dev)
     e_g = S.front_error(f_g, fr_t)
     closure_err = np.abs(np.where(c_g >= 0, c_g, T) - np.where(cl_t >= 0, cl_t, T)) / T
     # out-of-range queries must go to the LB
     oor = S.out_of_range_rows(3, 32)
-    f_o, c_o, use_o, _, lb_o = S.answer(net, oor, T, gate, device=dev)
+    f_o, c_o, use_o, _, lb_o = S.answer(ens, oor, T, gates, device=dev)
     total_s = net_s + lb_s
     plain_rph = sweep_out["plain"]["runs_per_hour"] if sweep_out else None
     batched_rph = sweep_out["batched"]["runs_per_hour"] if sweep_out else None
@@ -176,12 +176,15 @@ def surrogate_section(args, torch, dev, sweep_out):
     rph_amort = len(rows_t) / (total_s + (gen_s + train_s) * len(rows_t) / (len(rows) + len(rows_t)) ) * 3600
     return {"train_runs": len(rows), "heldout_runs": len(rows_t), "steps_per_run": T,
             "data_generation_s": round(gen_s + gen_t, 2), "train_s": round(train_s, 2),
-            "epochs": args.surr_epochs, "final_loss": hist[-1][1],
+            "epochs": args.surr_epochs, "ensemble_members": len(ens.members),
+            "final_loss": [h[-1][1] for h in hist],
             "network_only": {"front_err_mean": round(float(e_raw.mean()), 5),
                              "front_err_median": round(float(np.median(e_raw)), 5),
-                             "frac_over_2pct": round(float((e_raw > 0.02).mean()), 4)},
-            "gate_min_predicted_travel_lu": gate,
-            "gate_chosen_on": f"{nv} validation runs from the training seed (mean error <= 1%)",
+                             "frac_over_2pct": round(float((e_raw > 0.02).mean()), 4),
+                             "one_member_err_mean": round(float(e_one.mean()), 5),
+                             "one_member_err_median": round(float(np.median(e_one)), 5)},
+            "gates": {"min_predicted_travel_lu": gates[0], "max_relative_spread": round(gates[1], 5)},
+            "gates_chosen_on": f"{nv} training-seed runs held back from training (mean error <= 0.5%)",
             "answered_by_network": int(use.sum()),
             "gated": {"front_err_mean": round(float(e_g.mean()), 5),
                       "frac_over_2pct": round(float((e_g > 0.02).mean()), 4),
@@ -215,6 +218,7 @@ def main():
     ap.add_argument("--surr-train", type=int, default=4096)
     ap.add_argument("--surr-test", type=int, default=256)
     ap.add_argument("--surr-epochs", type=int, default=3000)
+    ap.add_argument("--surr-members", type=int, default=3, help="networks in the ensemble")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()

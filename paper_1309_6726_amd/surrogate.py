@@ -13,6 +13,10 @@ drives the pipeline:
     this makes every trajectory O(1) whatever its speed, so the loss tracks the
     front error relative to the travel; the network learns the deviation from
     the law (retardation by surface growth, pore closure, breakthrough);
+  * confidence: an ensemble of networks trained from different seeds answers
+    with its mean; a query goes to the lattice Boltzmann model when the
+    predicted travel is small or the members disagree (spread relative to the
+    travel), with both gates chosen on held-back training runs;
   * queries outside the training box go to the lattice Boltzmann model.
 """
 
@@ -144,6 +148,37 @@ class Surrogate:
         return y
 
 
+class Ensemble:
+    """K networks trained from different seeds (initial weights and minibatch
+    order).  The answer is the mean of the members' outputs; the spread of
+    their decoded fronts measures how far the ensemble can be trusted."""
+
+    def __init__(self, k: int = 3, **kw):
+        self.members = [Surrogate(**kw) for _ in range(k)]
+        self.lo, self.hi = self.members[0].lo, self.members[0].hi
+
+    def train(self, x, y, *, seed: int = 0, **kw):
+        """Member i is trained from seed + i; returns the loss histories."""
+        return [train(net, x, y, seed=seed + i, **kw) for i, net in enumerate(self.members)]
+
+    def predict(self, x):
+        return np.mean([net.predict(x).astype(np.float64) for net in self.members], axis=0)
+
+    def predict_with_spread(self, x, T: int):
+        """(mean outputs, relative spread): the largest over sample times of the
+        members' standard deviation of z(t_j), over max(predicted travel, 1 lu)."""
+        ys = np.stack([net.predict(x).astype(np.float64) for net in self.members])
+        y = ys.mean(axis=0)
+        fr = np.stack([decode(x, yk, T)[0] for yk in ys])
+        mean_travel = decode(x, y, T)[0][:, -1]
+        spread = fr.std(axis=0).max(axis=1) / np.maximum(mean_travel, 1.0)
+        return y, spread
+
+    def close(self):
+        for net in self.members:
+            net.close()
+
+
 def generate(seed: int, n: int, T: int, *, chunk: int = 512, device="cuda:0", log=None):
     """n sweep runs (sampler seed) advanced by the batched LB path.
     Returns (rows, x, fronts, closure, seconds)."""
@@ -213,6 +248,31 @@ def predict_runs(net: Surrogate, rows, T: int, *, device="cuda:0"):
     return fronts, closure, ok, lb_sec
 
 
+def choose_spread_gate(spread, err, target=0.005, min_frac=0.25) -> float:
+    """Largest relative spread such that the runs at or below it have mean
+    front error <= target and make up at least min_frac of the runs
+    (-1: none qualifies, every query goes to the lattice Boltzmann model)."""
+    order = np.argsort(spread, kind="stable")
+    n = np.arange(1, len(order) + 1)
+    cum = np.cumsum(np.asarray(err, dtype=np.float64)[order]) / n
+    ok = np.nonzero((cum <= target) & (n >= min_frac * len(order)))[0]
+    return float(np.asarray(spread)[order][ok[-1]]) if len(ok) else -1.0
+
+
+def choose_gates(model, x, fronts, T, target=0.005, min_frac=0.25):
+    """Both gates of an ensemble from held-back runs: the predicted-travel
+    gate (choose_gate) and the spread gate, each for mean error <= target."""
+    y, spread = model.predict_with_spread(x, T)
+    f, _ = decode(x, y, T)
+    err = front_error(f, fronts)
+
+    class _Fixed:
+        def predict(self, _x):
+            return y
+    return (choose_gate(_Fixed(), x, fronts, T, target, min_frac),
+            choose_spread_gate(spread, err, target, min_frac))
+
+
 def choose_gate(net: Surrogate, x, fronts, T, target=0.01, min_frac=0.25):
     """Smallest predicted travel z_hat(T) (lattice units) such that the runs
     predicted at or above it have mean front error <= target, chosen on runs
@@ -232,21 +292,29 @@ def choose_gate(net: Surrogate, x, fronts, T, target=0.01, min_frac=0.25):
     return float("inf")
 
 
-def answer(net: Surrogate, rows, T: int, gate: float, *, device="cuda:0"):
-    """Sweep queries answered by the network where it is in its box and
-    confident (predicted travel z_hat(T) >= gate lattice units), by the batched
-    lattice Boltzmann model otherwise.  Returns (fronts, closure, used_net mask,
-    net_seconds, lb_seconds)."""
+def answer(net, rows, T: int, gate, *, device="cuda:0"):
+    """Sweep queries answered by the network (a Surrogate or an Ensemble) where
+    it is in its box and confident, by the batched lattice Boltzmann model
+    otherwise.  gate: minimum predicted travel z_hat(T) in lattice units, or
+    for an ensemble (travel gate, spread gate).  Returns (fronts, closure,
+    used_net mask, net_seconds, lb_seconds)."""
     x = inputs.surrogate_inputs(rows)
     ok = in_box(x, net.lo, net.hi)
     fronts = np.zeros((len(rows), NSLOTS))
     closure = np.zeros(len(rows), dtype=np.int64)
     use = np.zeros(len(rows), dtype=bool)
+    g_travel, g_spread = (gate, None) if np.isscalar(gate) else gate
     t0 = time.perf_counter()
     if ok.any():
-        y = net.predict(x[ok]).astype(np.float64)
+        if g_spread is None:
+            y = net.predict(x[ok]).astype(np.float64)
+            spread = np.zeros(int(ok.sum()))
+        else:
+            y, spread = net.predict_with_spread(x[ok], T)
         f, c = decode(x[ok], y, T)
-        conf = f[:, -1] >= gate
+        conf = f[:, -1] >= g_travel
+        if g_spread is not None:
+            conf &= spread <= g_spread
         idx = np.nonzero(ok)[0][conf]
         fronts[idx], closure[idx] = f[conf], c[conf]
         use[idx] = True

@@ -111,3 +111,25 @@ def test_out_of_range_queries_go_to_lb(surr):
     probs = [inputs.sweep_problem(r, i, steps=T) for i, r in enumerate(rows)]
     f2, c2, _, _ = sweep.run_batched(probs, T, surr.NSLOTS)
     assert np.array_equal(f, f2) and np.array_equal(c, c2)
+
+
+def test_ensemble_mean_and_spread(surr):
+    """An ensemble answers with its members' mean; identical members have zero
+    spread, different members a positive one; the spread gate then decides."""
+    PT.say("[surrogate ensemble] 2 members, 40 queries")
+    ens = surr.Ensemble(2, max_batch=64, max_data=16)
+    p = inputs.mlp_init_params(5)
+    for m in ens.members:
+        m.set_params(p)
+    x, _ = _data(40, 6)
+    y, sp = ens.predict_with_spread(x, 10_000)
+    assert np.array_equal(y, ens.members[0].predict(x).astype(np.float64))
+    assert np.all(sp == 0.0)
+    ens.members[1].set_params(inputs.mlp_init_params(6))
+    y, sp = ens.predict_with_spread(x, 10_000)
+    y0, y1 = (m.predict(x).astype(np.float64) for m in ens.members)
+    assert np.allclose(y, 0.5 * (y0 + y1), rtol=0, atol=1e-12)
+    assert np.all(sp > 0.0)
+    rows = inputs.sweep_params(4, 6)
+    _, _, use, _, _ = surr.answer(ens, rows, 200, (0.0, -1.0))
+    assert not use.any()  # a negative spread gate sends everything to the LB

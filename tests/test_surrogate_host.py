@@ -53,6 +53,19 @@ def test_gate_picks_smallest_travel_meeting_target():
     assert g > true[9, -1] * 0.5
 
 
+def test_spread_gate_keeps_the_agreeing_runs():
+    """Runs sorted by ensemble spread: the gate is the largest spread whose
+    runs at or below it average <= target error, with a minimum coverage."""
+    spread = np.array([0.01, 0.02, 0.03, 0.04, 0.5, 0.6, 0.7, 0.8])
+    err = np.array([0.001, 0.002, 0.003, 0.004, 0.05, 0.06, 0.07, 0.08])
+    g = S.choose_spread_gate(spread, err, target=0.005, min_frac=0.25)
+    assert g == 0.04
+    assert S.choose_spread_gate(spread, err, target=0.0005, min_frac=0.25) == -1.0
+    # the mean error over the selected runs is what counts, not each run's
+    err2 = np.array([0.009, 0.001, 0.001, 0.001, 0.05, 0.06, 0.07, 0.08])
+    assert S.choose_spread_gate(spread, err2, target=0.005, min_frac=0.25) == 0.04
+
+
 def test_out_of_range_rows_are_outside_the_box():
     lo, hi = inputs.surrogate_box()
     rows = S.out_of_range_rows(3, 32)
