@@ -202,14 +202,14 @@ lbm_status queue_steps(lbm_sim* s, long long n) {
   a.nsegs = (p.ny + s->sy - 1) / s->sy;
   a.solute = s->L.solute;
   a.react = s->L.react;
-  a.omega = (float)(1.0 / p.tau);
-  a.tau = (float)p.tau;
-  a.G = (float)p.G;
-  a.Gads1 = (float)p.G_ads[0];
-  a.Gads2 = (float)p.G_ads[1];
-  a.ax = (float)p.accel[0];
-  a.ay = (float)p.accel[1];
-  a.omega_g = s->L.solute ? (float)(1.0 / p.tau_g) : 0.0f;
+  a.omega = 1.0 / p.tau;
+  a.tau = p.tau;
+  a.G = p.G;
+  a.Gads1 = p.G_ads[0];
+  a.Gads2 = p.G_ads[1];
+  a.ax = p.accel[0];
+  a.ay = p.accel[1];
+  a.omega_g = s->L.solute ? 1.0 / p.tau_g : 0.0;
   a.k_r = p.k_r;
   a.threshold = p.threshold;
   a.c_eq = p.c_eq;
@@ -843,14 +843,14 @@ StepArgs instance_args(const lbm_batch* b, int i, int parity) {
   a.remap = 0;
   a.solute = L.solute;
   a.react = L.react;
-  a.omega = (float)(1.0 / p.tau);
-  a.tau = (float)p.tau;
-  a.G = (float)p.G;
-  a.Gads1 = (float)p.G_ads[0];
-  a.Gads2 = (float)p.G_ads[1];
-  a.ax = (float)p.accel[0];
-  a.ay = (float)p.accel[1];
-  a.omega_g = L.solute ? (float)(1.0 / p.tau_g) : 0.0f;
+  a.omega = 1.0 / p.tau;
+  a.tau = p.tau;
+  a.G = p.G;
+  a.Gads1 = p.G_ads[0];
+  a.Gads2 = p.G_ads[1];
+  a.ax = p.accel[0];
+  a.ay = p.accel[1];
+  a.omega_g = L.solute ? 1.0 / p.tau_g : 0.0;
   a.k_r = p.k_r;
   a.threshold = p.threshold;
   a.c_eq = p.c_eq;

@@ -36,10 +36,11 @@ struct StepArgs {
   unsigned bit_p1;    // pending bit written by step n-1 (solid in state n)
   unsigned bit_p2;    // pending bit written by step n-2 (folded into bit0 now)
   unsigned bit_cur;   // pending bit this step writes
-  float omega;        // 1/tau
-  float tau;
-  float G, Gads1, Gads2, ax, ay;
-  float omega_g;      // 1/tau_g
+  // model parameters in FP64 (kernel arguments stay in scalar registers)
+  double omega;       // 1/tau
+  double tau;
+  double G, Gads1, Gads2, ax, ay;
+  double omega_g;     // 1/tau_g
   double k_r, threshold;
   double c_eq;        // saturation concentration of the reaction (0: plain first order)
   double c_hold;      // held concentration of the source region x < hold_x

@@ -55,6 +55,12 @@
 
 #include "lbm_dev.h"
 
+// Multiply-adds are fused only where one source expression states them: the
+// compiler may peel or duplicate loop iterations, and fusion chosen per copy
+// would make the rounding of a node depend on which copy computes it (and so
+// on the launch shape).
+#pragma clang fp contract(on)
+
 namespace lbmdev {
 
 template <typename R>
