@@ -43,8 +43,8 @@ def wall_adjacent(solid: np.ndarray) -> np.ndarray:
 # byte.
 BYTES_PER_LUP = {"populations": 185, "moments": 89}
 BYTES_PER_WALL_NODE = 16  # FP64 precipitate read and written at wall-adjacent fluid nodes
-KERNEL = {"populations": "k_step<true,true,double,KIND_POP>",
-          "moments": "k_step<true,true,double,KIND_MM>"}
+KERNEL = {"populations": "k_step<true,true,false,double,KIND_POP>",
+          "moments": "k_step<true,true,false,double,KIND_MM>"}
 
 
 def algorithmic_bytes(solid: np.ndarray, scheme: str) -> tuple:
