@@ -78,6 +78,15 @@ __device__ __forceinline__ R sum9(const float* v) {
 // encoding: vmcnt[3:0] and [15:14], expcnt[6:4], lgkmcnt[11:8]).
 #define VMCNT0 0x0F70
 
+typedef unsigned v2u __attribute__((ext_vector_type(2)));
+
+// Raw buffer descriptor (stride 0, no format conversion) over bytes [0, extent)
+// of base.  Word 3 is the value the gfx9-family buffer instructions take for
+// untyped dword access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned extent) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)extent, 0x00020000);
+}
+
 // Workgroup-wide LDS barrier that leaves outstanding global memory operations
 // in flight (only LDS traffic is ordered); a single-wave workgroup needs no
 // s_barrier at all.
@@ -151,12 +160,32 @@ __device__ __forceinline__ void sc_velocities(R tau, R rho1, R rho2, R j1x, R j1
 // equilibrium at c_hold), threshold test, and push of the solute populations
 // (bounce-back at solid axis neighbours).  sf: solid flags of the axis
 // neighbours 1..4.
+// What solute_step leaves for memory every step: the five pushed populations
+// with their element offsets in gout, and the new precipitate of the node
+// (wm: the node is next to a wall, so m changed).
+struct SoluteOut {
+  float g[5];
+  unsigned off[5];
+  double m;
+  bool wm;
+};
+
+template <bool REACT>
+__device__ __forceinline__ void store_solute(const StepArgs& a, const SoluteOut& o, unsigned idx) {
+  float* __restrict__ go = a.gout;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) go[o.off[q]] = o.g[q];
+  if (REACT && o.wm) a.m[idx] = o.m;
+}
+
 template <bool REACT, bool VAR, typename R>
 __device__ __forceinline__ void solute_step(const StepArgs& a, const float* g, R ux, R uy,
                                             R rho1, R rho2, const float* sf, double m_cur,
                                             unsigned P, unsigned idx, unsigned iE, unsigned iN,
                                             unsigned iW, unsigned iS, int xc, int y, bool& ev,
-                                            int& evx, int& evy) {
+                                            int& evx, int& evy, SoluteOut& so) {
+  so.wm = false;
+  so.m = 0.0;
   // VAR = false: the plain model (D2Q5, c_eq = 0, no held source)
   const bool q4 = VAR && a.q4 != 0;
   const R WQ = q4 ? R(0.25) : R(1) / R(6), CQ = q4 ? R(2) : R(3);
@@ -183,7 +212,8 @@ __device__ __forceinline__ void solute_step(const StepArgs& a, const float* g, R
         keep = 1.0 - rr;
       }
       const double mm = m_cur + dm;
-      a.m[idx] = mm;
+      so.m = mm;
+      so.wm = true;
 #pragma unroll
       for (int q = 0; q < 5; ++q) gs[q] *= (R)keep;
       if (mm > a.threshold) {
@@ -203,12 +233,14 @@ __device__ __forceinline__ void solute_step(const StepArgs& a, const float* g, R
     gs[4] = WQ * Ch * (R(1) - CQ * uy);
     gs[0] = q4 ? R(0) : (R(1) - R(4) * WQ) * Ch;
   }
-  float* __restrict__ go = a.gout;
-  go[idx] = (float)gs[0];
-  if (sf[1] != 0.0f) go[3 * P + idx] = (float)gs[1]; else go[1 * P + iE] = (float)gs[1];
-  if (sf[2] != 0.0f) go[4 * P + idx] = (float)gs[2]; else go[2 * P + iN] = (float)gs[2];
-  if (sf[3] != 0.0f) go[1 * P + idx] = (float)gs[3]; else go[3 * P + iW] = (float)gs[3];
-  if (sf[4] != 0.0f) go[2 * P + idx] = (float)gs[4]; else go[4 * P + iS] = (float)gs[4];
+  // push; at a solid axis neighbour the value bounces into the opposite link
+#pragma unroll
+  for (int q = 0; q < 5; ++q) so.g[q] = (float)gs[q];
+  so.off[0] = idx;
+  so.off[1] = sf[1] != 0.0f ? 3 * P + idx : 1 * P + iE;
+  so.off[2] = sf[2] != 0.0f ? 4 * P + idx : 2 * P + iN;
+  so.off[3] = sf[3] != 0.0f ? 1 * P + idx : 3 * P + iW;
+  so.off[4] = sf[4] != 0.0f ? 2 * P + idx : 4 * P + iS;
 }
 
 // One lane per wavefront reserves event-log slots for every lane that marked
@@ -450,9 +482,12 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int strip, int seg,
           collide_push(f, 0u, rho1, v1x, v1y);
           collide_push(f + 9, 9u, rho2, v2x, v2y);
         }
-        if (SOLUTE)
+        if (SOLUTE) {
+          SoluteOut so;
           solute_step<REACT, VAR, R>(a, g, ux, uy, rho1, rho2, sf, m_cur, P, idx, iE, iN, iW, iS, xc, y,
-                                ev, evx, evy);
+                                ev, evx, evy, so);
+          store_solute<REACT>(a, so, idx);
+        }
       }
     }
     if (REACT) log_events(a, ev, evx, evy);
@@ -542,10 +577,19 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
   const int nrows = ye - ys + 4;
   const unsigned SPREV = 1u | a.bit_p2;    // solid in state n-1
   const unsigned SCUR = SPREV | a.bit_p1;  // solid in state n
-  const float* __restrict__ Min = a.fin;
-  const float* __restrict__ gin = a.gin;
-  const uint8_t* __restrict__ maskp = a.mask;
   const R WA = R(1) / R(9), WD = R(1) / R(36), WR = R(4) / R(9);
+  // Buffer descriptors: one per array, plane q at scalar offset q * P * 4
+  // bytes, so an access costs one 32-bit lane offset per row instead of a
+  // 64-bit address per plane.  The extent covers every plane the kernel
+  // touches: the hardware checks lane offset plus scalar offset against it,
+  // and a lane beyond it reads 0 and drops its store.
+  const unsigned PB = P * 4u;
+  const auto rMin = make_rsrc(a.fin, 6u * PB);
+  const auto rMout = make_rsrc(a.fout, 6u * PB);
+  const auto rGin = make_rsrc(a.gin, SOLUTE ? 5u * PB : 0u);
+  const auto rGout = make_rsrc(a.gout, SOLUTE ? 5u * PB : 0u);
+  const auto rMask = make_rsrc(a.mask, P);
+  const auto rPrec = make_rsrc(a.m, REACT ? 2u * PB : 0u);
 
   auto row_y = [&](int k) {
     int yr = ys - 2 + k;
@@ -555,38 +599,46 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
   };
   auto sol = [](unsigned pk, int sh, unsigned bits) { return ((pk >> sh) & bits) != 0u; };
   auto mask_at = [&](int k) -> unsigned {
-    return (active && k < nrows) ? (unsigned)maskp[(unsigned)row_y(k) * (unsigned)nx + (unsigned)xc] : 1u;
+    return (active && k < nrows)
+               ? (unsigned)__builtin_amdgcn_raw_buffer_load_b8(
+                     rMask, (int)((unsigned)row_y(k) * (unsigned)nx + (unsigned)xc), 0, 0)
+               : 1u;
   };
   using lds_ptr = __attribute__((address_space(3))) void*;
-  auto to_lds = [&](const float* src, int buf, int slot) {
-    __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr)&pf[buf][slot][0], 4, 0, 0);
+  // one dword per lane at byte offset voff + soff into prefetch slot (buf, slot)
+  auto to_lds = [&](__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, int buf, int slot) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)&pf[buf][slot][0], 4, (int)voff, (int)soff,
+                                             0, 0);
   };
-  // copy row k's moments (fluid nodes of state n-1) and row k-2's solute
+  // Copy row k's moments (fluid nodes of state n-1) and row k-2's solute
   // and precipitate (fluid owned nodes, precipitate only next to a wall of
-  // state n) into buffer buf; the flags say which lanes copied what
+  // state n) into buffer buf.  Every lane issues every load; a lane with
+  // nothing to copy gives a lane offset past every extent (such an offset
+  // stays out of range whatever scalar offset is added), so the hardware
+  // writes 0 to its slot without touching memory, and the reader needs no
+  // select.
+  constexpr unsigned NONE = 0xFFFFFFF0u;
   auto prefetch = [&](int buf, int k, unsigned own_k, unsigned pkm3, unsigned pkm2,
-                      unsigned pkm1, bool& got_m, bool& got_g, bool& got_p) {
-    got_m = active && k < nrows && !(own_k & SPREV);
-    if (got_m) {
-      const unsigned i = (unsigned)row_y(k) * (unsigned)nx + (unsigned)xc;
+                      unsigned pkm1) {
+    if (k >= nrows) return;
+    const bool got_m = active && !(own_k & SPREV);
+    const unsigned vm = got_m ? 4u * ((unsigned)row_y(k) * (unsigned)nx + (unsigned)xc) : NONE;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) to_lds(Min + q * P + i, buf, q);
-    }
-    const bool crow = k >= 4 && k < nrows && owner;
-    const unsigned ownC = pkm2 & 0xFFu;
-    got_g = SOLUTE && crow && !(ownC & SPREV);
-    got_p = REACT && crow && !(ownC & SCUR) &&
-            (sol(pkm2, 16, SCUR) || sol(pkm1, 0, SCUR) || sol(pkm2, 8, SCUR) || sol(pkm3, 0, SCUR));
-    if (got_g || got_p) {
+    for (int q = 0; q < 6; ++q) to_lds(rMin, vm, (unsigned)q * PB, buf, q);
+    if (SOLUTE && k >= 4) {
+      const unsigned ownC = pkm2 & 0xFFu;
       const unsigned i = (unsigned)(ys + k - 4) * (unsigned)nx + (unsigned)xc;
-      if (got_g) {
+      const bool got_g = owner && !(ownC & SPREV);
+      const unsigned vg = got_g ? 4u * i : NONE;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) to_lds(gin + q * P + i, buf, 6 + q);
-      }
-      if (got_p) {
-        const float* mp = (const float*)(a.m + i);
-        to_lds(mp, buf, 11);
-        to_lds(mp + 1, buf, 12);
+      for (int q = 0; q < 5; ++q) to_lds(rGin, vg, (unsigned)q * PB, buf, 6 + q);
+      if (REACT) {
+        const bool got_p =
+            owner && !(ownC & SCUR) &&
+            (sol(pkm2, 16, SCUR) || sol(pkm1, 0, SCUR) || sol(pkm2, 8, SCUR) || sol(pkm3, 0, SCUR));
+        const unsigned vp = got_p ? 8u * i : NONE;
+        to_lds(rPrec, vp, 0u, buf, 11);
+        to_lds(rPrec, vp, 4u, buf, 12);
       }
     }
   };
@@ -596,8 +648,7 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
   unsigned pk_m3 = SOLID3, pk_m2 = SOLID3, pk_m1 = SOLID3;
   unsigned pk_0 = pack_row_mask(mask_at(0));
   unsigned m_ahead = mask_at(1);  // raw mask of row k+1 (then k+2)
-  bool got_m, got_g, got_p;
-  prefetch(0, 0, pk_0 & 0xFFu, pk_m3, pk_m2, pk_m1, got_m, got_g, got_p);
+  prefetch(0, 0, pk_0 & 0xFFu, pk_m3, pk_m2, pk_m1);
 
   R acc0[6], acc1[6];  // (rho1, j1x, j1y, rho2, j2x, j2y) of rows k and k-1
 #pragma unroll
@@ -615,16 +666,13 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
     // everything requested during the previous iteration has arrived
     __builtin_amdgcn_s_waitcnt(VMCNT0);
     const unsigned pk_p1 = pack_row_mask(m_ahead);
-    // what the data in buffer buf holds (lanes that did not copy read 0)
-    const bool cur_m = got_m, cur_g = got_g, cur_p = got_p;
-    auto take = [&](int slot, bool got) {
-      const float v = pf[buf][slot][t];  // read unconditionally, then select
-      return got ? v : 0.0f;
-    };
+    // buffer buf holds row k's moments and row k-2's solute and precipitate
+    // (0 where nothing was copied)
+    auto take = [&](int slot) { return pf[buf][slot][t]; };
     const unsigned own0 = pk_0 & 0xFFu;
     // requests for the next iteration: row k+1's moments, row k-1's solute,
     // the mask of row k+2
-    prefetch(buf ^ 1, k + 1, pk_p1 & 0xFFu, pk_m2, pk_m1, pk_0, got_m, got_g, got_p);
+    prefetch(buf ^ 1, k + 1, pk_p1 & 0xFFu, pk_m2, pk_m1, pk_0);
     m_ahead = mask_at(k + 2);
 
     const bool crow = k >= 4 && owner;
@@ -646,8 +694,8 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
     for (int c = 0; c < 2; ++c) {
       // with u3 = 3 v: w rho (1 + 3 e.v + 9/2 (e.v)^2 - 3/2 v^2)
       //              = w rho (cc + e3 (1 + e3 / 2)), e3 = e . u3, cc = 1 - u3^2 / 6
-      const R rho = (R)take(3 * c, cur_m);
-      const R ux = R(3) * (R)take(3 * c + 1, cur_m), uy = R(3) * (R)take(3 * c + 2, cur_m);
+      const R rho = (R)take(3 * c);
+      const R ux = R(3) * (R)take(3 * c + 1), uy = R(3) * (R)take(3 * c + 2);
       const R cc = fmar(ux * ux + uy * uy, R(-1) / R(6), R(1));
       const R ra = WA * rho, rd = WD * rho;
       auto out = [&](R r, R e3) { return r * fmar(e3, fmar(e3, R(0.5), R(1)), cc); };
@@ -712,7 +760,11 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
       const unsigned idx = idxC;
       float gv[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) gv[q] = take(6 + q, cur_g);
+      for (int q = 0; q < 5; ++q) gv[q] = take(6 + q);
+      // outgoing moments; zero at a node solid in state n, which no reader of
+      // the next state takes as fluid.  Every owned lane stores, so each plane
+      // is written as whole rows rather than lines with holes at solids.
+      float mo[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       if (ownC & SCUR) {
         if (REACT) {
           if (ownC & a.bit_p1) {
@@ -742,25 +794,37 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
         R v1x, v1y, v2x, v2y, ux, uy;
         sc_velocities<R>((R)a.tau, rC[0], rC[3], rC[1], rC[2], rC[4], rC[5], F1x, F1y, F2x, F2y,
                          v1x, v1y, v2x, v2y, ux, uy);
-        float* __restrict__ fo = a.fout;
-        fo[idx] = (float)rC[0];
-        fo[P + idx] = (float)v1x;
-        fo[2 * P + idx] = (float)v1y;
-        fo[3 * P + idx] = (float)rC[3];
-        fo[4 * P + idx] = (float)v2x;
-        fo[5 * P + idx] = (float)v2y;
+        mo[0] = (float)rC[0];
+        mo[1] = (float)v1x;
+        mo[2] = (float)v1y;
+        mo[3] = (float)rC[3];
+        mo[4] = (float)v2x;
+        mo[5] = (float)v2y;
         if (SOLUTE) {
           const int yd = y == 0 ? ny - 1 : y - 1;
           const int yu = y == ny - 1 ? 0 : y + 1;
           const unsigned iE = (unsigned)y * nx + xr, iW = (unsigned)y * nx + xl;
           const unsigned iN = (unsigned)yu * nx + xc, iS = (unsigned)yd * nx + xc;
           const double mC =
-              cur_p ? __hiloint2double(__float_as_int(pf[buf][12][t]), __float_as_int(pf[buf][11][t]))
+              REACT ? __hiloint2double(__float_as_int(pf[buf][12][t]), __float_as_int(pf[buf][11][t]))
                     : 0.0;
+          SoluteOut so;
           solute_step<REACT, VAR, R>(a, gv, ux, uy, rC[0], rC[3], sf, mC, P, idx, iE, iN, iW, iS, xc,
-                                y, ev, evx, evy);
+                                y, ev, evx, evy, so);
+#pragma unroll
+          for (int q = 0; q < 5; ++q)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(so.g[q]), rGout,
+                                                  (int)(4u * so.off[q]), 0, 0);
+          if (REACT && so.wm) {
+            const v2u mb = {(unsigned)__double2loint(so.m), (unsigned)__double2hiint(so.m)};
+            __builtin_amdgcn_raw_buffer_store_b64(mb, rPrec, (int)(8u * idx), 0, 0);
+          }
         }
       }
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(mo[q]), rMout, (int)(4u * idx),
+                                              (int)((unsigned)q * PB), 0);
     }
     if (REACT) log_events(a, ev, evx, evy);
 
