@@ -253,7 +253,7 @@ def main():
         with HIP events on the library's stream."""
         sim = lbm.Sim.from_problem(prob, device=dev, stream=stream, scheme=scheme)
         if tile == "auto":
-            (tx, sy), _ = sim.autotune(steps=10)
+            (tx, sy), _ = sim.autotune(steps=50)
         else:
             tx, sy = (int(v) for v in tile.lower().split("x"))
             sim.set_tile(tx, sy)

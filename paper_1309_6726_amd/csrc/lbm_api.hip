@@ -672,7 +672,7 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   const int txs[] = {64, 128, 256};
-  const int sys[] = {8, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128};
+  const int sys[] = {6, 8, 9, 10, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128};
   int btx = s->tx, bsy = s->sy;
   float best = 1e30f;
   for (int tx : txs) {
@@ -879,8 +879,9 @@ lbm_status batch_configure(lbm_batch* b) {
   const int own = owned_cols(b->tx, batch_moments(b));
   for (int i = 0; i < b->n; ++i) {
     const int ns = (b->p[i].nx + own - 1) / own, nq = (b->p[i].ny + b->sy - 1) / b->sy;
-    for (int s = 0; s < ns; ++s)
-      for (int q = 0; q < nq; ++q) order.push_back(make_int4(i, s, q, 0));
+    // segment-major inside an instance, like the single-lattice step
+    for (int q = 0; q < nq; ++q)
+      for (int s = 0; s < ns; ++s) order.push_back(make_int4(i, s, q, 0));
   }
   const int T = (int)order.size();
   if (T > b->max_tiles) return fail(LBM_EINVAL, "tile list exceeds its buffer");
@@ -1213,7 +1214,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* tx_out, int3
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   const int txs[] = {64, 128, 256};
-  const int sys[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 80};
+  const int sys[] = {8, 9, 10, 12, 16, 20, 24, 32, 40, 48, 64, 80};
   int btx = b->tx, bsy = b->sy;
   float best = 1e30f;
   for (int tx : txs) {

@@ -848,8 +848,10 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
 
 // XCD-aware order: the hardware hands block b to XCD b mod 8, so XCD x
 // receives q + (x < r) of T blocks (q = T / 8, r = T mod 8).  Give each XCD a
-// contiguous run of tiles, so vertically adjacent segments of a strip share
-// one L2 and their halo rows are fetched from HBM once.
+// contiguous run of tiles.  Tiles are numbered segment-major, so a run is a
+// horizontal band of full rows: the waves resident on one XCD read whole
+// rows together (DRAM pages stay open), and both halo directions are shared
+// in one L2 except at the band's edges.
 __host__ __device__ inline int xcd_tile(int b, int T) {
   const int q = T >> 3, r = T & 7, x = b & 7, j = b >> 3;
   return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
@@ -869,8 +871,8 @@ k_step(const StepArgs a) {
   extern __shared__ char lds_raw[];
   const int T = a.nstrips * a.nsegs;
   const int tile = a.remap ? xcd_tile(blockIdx.x, T) : (int)blockIdx.x;
-  const int strip = tile / a.nsegs;
-  run_tile<SOLUTE, REACT, VAR, R, KIND>(a, strip, tile - strip * a.nsegs, lds_raw);
+  const int seg = tile / a.nstrips;
+  run_tile<SOLUTE, REACT, VAR, R, KIND>(a, tile - seg * a.nstrips, seg, lds_raw);
 }
 
 // Batched step: one launch advances every instance of a batch by one step.
