@@ -49,6 +49,19 @@ def test_workspace_and_param_checks(L):
         assert L.lib().lbm_last_error()
 
 
+def test_size_limit(L):
+    """32-bit element offsets: 23 population planes of P = ceil64(nx ny)
+    elements must stay below 2^31.  9472 x 9856 (the lattice of the GPU
+    maximum-size test) is accepted, three more rows are refused."""
+    p = inputs.config1().params.replace(nx=9472, ny=9856, W=0, x_in=0, x_out=0, y0=0)
+    P = (p.nx * p.ny + 63) // 64 * 64
+    assert 23 * P <= 2**31 - 1 < 23 * (P + 3 * p.nx)
+    assert L.workspace_bytes(p) > 0
+    with pytest.raises(L.LbmError) as e:
+        L.workspace_bytes(p.replace(ny=p.ny + 3))
+    assert e.value.status == L.LBM_EINVAL
+
+
 def test_strerror(L):
     lib = L.lib()
     for s in (0, -1, -2, -3, -4, -5):
