@@ -1,6 +1,6 @@
-"""Pins of the reaction and solute-lattice variants of the oracle (survey's
-next rows; section "LB models": precipitation at the surface on an
-advection-diffusion BGK lattice):
+"""Pins of the reaction and solute-lattice variants of the oracle (section
+"LB models": precipitation at the surface on an advection-diffusion BGK
+lattice):
   * D2Q4 solute lattice: exact variance of a point source at rest;
   * saturation concentration c_eq: closed form of an isolated reacting node;
   * held source: fixed point and the interior of the held region."""
