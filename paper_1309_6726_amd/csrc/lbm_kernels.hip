@@ -254,7 +254,10 @@ __device__ __forceinline__ void log_events(const StepArgs& a, bool ev, int evx, 
     if (lane == leader) base = atomicAdd(a.ev_count, (unsigned long long)__popcll(bal));
     base = __shfl(base, leader);
     if (ev) {
-      const unsigned long long e = base + __popcll(bal & ((1ull << lane) - 1ull));
+      // events of lower lanes in this row come first
+      const unsigned below = __builtin_amdgcn_mbcnt_hi(
+          (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+      const unsigned long long e = base + below;
       if ((long long)e < a.ev_cap) {
         a.ev[e].x = evx;
         a.ev[e].y = evy;
