@@ -171,7 +171,11 @@ lbm_status lbm_events(lbm_sim* sim, int64_t first, lbm_event* buf, int64_t cap, 
  * turned solid at the end of step s, kept for the two steps after it, so a
  * state at step n may also hold the marks of steps n-1 and n-2), then if
  * reaction: m double[N], solid step int32[N] (-1 fluid), removed float[3][N],
- * events lbm_event[n_events].  Populations are always saved: in the moment
+ * events lbm_event[n_events].  In a state at step n, the population slots of
+ * nodes already solid before (bit0, or the mark of step n-2) carry no
+ * information: no step reads them, and a step may leave them or write zeros
+ * there.  A node marked at the end of step n-1 still holds the populations it
+ * carried, which step n books.  Populations are always saved: in the moment
  * scheme (lbm_set_scheme) the moments are first unpacked into populations
  * and the run goes on from those, so a loaded checkpoint continues bit for
  * bit like the run that saved it. */
