@@ -349,6 +349,66 @@ def test_edge_lattices(lbm, oracle_mod):
         _fields_cmp(sim, orc, name)
 
 
+def _degenerate(name, nx, ny):
+    """Geometries at the edges of what the step meets: every fluid node with
+    four solid axis neighbours, fluid nodes enclosed on all eight sides, a
+    channel one node wide, and wall bumps that grow across the periodic seam."""
+    s = np.zeros((ny, nx), np.uint8)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    if name == "checkerboard":
+        s[(xx + yy) % 2 == 1] = 1
+    elif name == "isolated nodes":
+        s[:] = 1
+        s[1::3, 1::3] = 0
+    elif name == "one-wide channel":
+        s[:] = 1
+        s[ny // 2, :] = 0
+    elif name == "seam":
+        s[:2, :] = 1
+        s[-2:, :] = 1
+        s[2:4, :2] = 1          # bumps on both sides of x = 0
+        s[2:4, nx - 2:] = 1
+        s[ny - 4:ny - 2, 0] = 1
+        s[ny - 4:ny - 2, nx - 1] = 1
+    return s
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+@pytest.mark.parametrize("name", ["checkerboard", "isolated nodes", "one-wide channel", "seam"])
+def test_degenerate_geometries(lbm, oracle_mod, name, tau):
+    """Degenerate geometries against the oracle, both schemes (tau = 1 runs
+    the moment step, 0.8 the population step): fields, events and ledgers
+    after 1, 5 and 40 steps.  The reaction runs at its limit 4 k_r = 1 (a node
+    with four solid axis neighbours consumes all its solute) and the
+    threshold is low, so nodes grow within the run."""
+    nx, ny = 67, 23
+    solid = _degenerate(name, nx, ny)
+    rng = np.random.default_rng(nx * ny + len(name))
+    fl = solid == 0
+    r1 = np.where(fl, 0.8 + 0.2 * rng.random((ny, nx)), 0.0)
+    r2 = np.where(fl, 0.05 + 0.1 * rng.random((ny, nx)), 0.0)
+    c = np.where(fl, 0.3 + 0.4 * rng.random((ny, nx)), 0.0)
+    p = inputs.Params(nx=nx, ny=ny, tau=tau, G=1.6, G_ads1=-0.33, G_ads2=0.33, tau_g=0.65,
+                      k_r=0.25, threshold=0.35, accel_x=1e-5)
+    PT.say(f"[degenerate] {name} tau {tau}")
+    sim = lbm.Sim(p, solid, r1, r2, c, tile=(64, 8))
+    orc = oracle_mod.Oracle(p, solid, r1, r2, c)
+    for n in (1, 5, 40):
+        sim.step(n - orc.steps)
+        orc.step(n - orc.steps)
+        _fields_cmp(sim, orc, f"{name} tau {tau} step {n}", rho_tol=2e-5, u_tol=2e-5,
+                    conc_tol=2e-5, m_tol=1e-6)
+        assert PT.event_set(sim.events()) == PT.event_set(orc.events()), (name, n)
+    go, oo = sim.observe(), orc.observe()
+    for k in ("solute", "precipitate", "solute_removed"):
+        assert abs(go[k] - oo[k]) <= 1e-5 * max(1.0, abs(oo[k])), k
+    for sc in range(2):
+        assert abs(go["mass"][sc] - oo["mass"][sc]) <= 1e-5 * max(1.0, oo["mass"][sc])
+        assert abs(go["mass_removed"][sc] - oo["mass_removed"][sc]) <= 1e-5 * max(1.0, oo["mass_removed"][sc])
+    assert go["n_solid"] == oo["n_solid"]
+    assert len(orc.events()) > 0, name
+
+
 def test_error_paths(lbm):
     L = lbm
     prob = inputs.config0()
