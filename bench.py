@@ -96,7 +96,10 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms / 1e3) / 1e9
 
 
-def cpu_baseline(prob, steps: int):
+def cpu_baseline(prob, steps: int, single_steps: int = 5):
+    """The oracle on the host: `steps` steps on all OpenMP threads, then
+    `single_steps` more on one thread."""
+    import ctypes
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     orc = O.Oracle.from_problem(prob)
@@ -105,9 +108,19 @@ def cpu_baseline(prob, steps: int):
     orc.step(steps)
     dt = time.perf_counter() - t0
     N = prob.params.nx * prob.params.ny
-    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} steps of the full {prob.params.nx}x{prob.params.ny} preform "
-                      f"(after 1 untimed step), FP64, OpenMP {threads} threads, {dt:.1f} s"}
+    out = {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} steps of the full {prob.params.nx}x{prob.params.ny} preform "
+                     f"(after 1 untimed step), FP64, OpenMP {threads} threads, {dt:.1f} s"}
+    if single_steps > 0:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        orc.step(single_steps)
+        d1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        out["single_thread"] = {"value": N * single_steps / d1 / 1e6, "unit": "MLUPS",
+                                "steps": single_steps, "seconds": round(d1, 2)}
+    return out
 
 
 def sweep_section(args, torch, dev):
