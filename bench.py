@@ -169,7 +169,7 @@ def surrogate_section(args, torch, dev, sweep_out):
     nv = len(rows) // 8
     hist = ens.train(x[:-nv], y[:-nv], epochs=args.surr_epochs, lr=2e-3,
                      log_every=args.surr_epochs)
-    gates = S.choose_gates(ens, x[-nv:], fr[-nv:], T, target=0.005)
+    gates = S.choose_gates(ens, x[-nv:], fr[-nv:], T, target=args.surr_gate_target)
     train_s = time.perf_counter() - t0
     # raw networks on the held-out runs: one member, and the ensemble mean
     e_one = S.front_error(S.decode(x_t, ens.members[0].predict(x_t).astype(np.float64), T)[0], fr_t)
@@ -197,7 +197,8 @@ def surrogate_section(args, torch, dev, sweep_out):
                              "one_member_err_mean": round(float(e_one.mean()), 5),
                              "one_member_err_median": round(float(np.median(e_one)), 5)},
             "gates": {"min_predicted_travel_lu": gates[0], "max_relative_spread": round(gates[1], 5)},
-            "gates_chosen_on": f"{nv} training-seed runs held back from training (mean error <= 0.5%)",
+            "gates_chosen_on": f"{nv} training-seed runs held back from training "
+                               f"(mean error <= {100 * args.surr_gate_target:g}%)",
             "answered_by_network": int(use.sum()),
             "gated": {"front_err_mean": round(float(e_g.mean()), 5),
                       "frac_over_2pct": round(float((e_g > 0.02).mean()), 4),
@@ -232,6 +233,8 @@ def main():
     ap.add_argument("--surr-test", type=int, default=256)
     ap.add_argument("--surr-epochs", type=int, default=3000)
     ap.add_argument("--surr-members", type=int, default=3, help="networks in the ensemble")
+    ap.add_argument("--surr-gate-target", type=float, default=0.01,
+                    help="mean front error the gates are chosen for on held-back runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
