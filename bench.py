@@ -62,7 +62,7 @@ def algorithmic_bytes(solid: np.ndarray, scheme: str) -> tuple:
 
 def measured_traffic(tile, scheme):
     """HBM bytes per launch from the committed PMC summary, only if it was
-    taken on this kernel source, scheme and launch shape."""
+    taken on this kernel source and scheme, for this launch shape."""
     path = os.path.join(ROOT, "profiles", f"k_step_{scheme}_preform2048_traffic.json")
     src = os.path.join(ROOT, "paper_1309_6726_amd", "csrc", "lbm_kernels.hip")
     try:
@@ -72,11 +72,12 @@ def measured_traffic(tile, scheme):
             sha = hashlib.sha256(fh.read()).hexdigest()
     except OSError:
         return None
-    if rec.get("kernel_src_sha256") != sha or list(rec.get("tile", [])) != list(tile):
+    if rec.get("kernel_src_sha256") != sha or rec.get("kernel") != KERNEL[scheme]:
         return None
-    if rec.get("kernel") != KERNEL[scheme]:
+    t = rec.get("by_tile", {}).get(f"{tile[0]}x{tile[1]}")
+    if t is None:
         return None
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
 
 
 def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
