@@ -60,7 +60,11 @@ def algorithmic_bytes(solid: np.ndarray, scheme: str) -> tuple:
     return per_lup, fluid_only, wall
 
 
-def measured_traffic(tile, scheme):
+def traffic_key(tile, nt) -> str:
+    return f"{tile[0]}x{tile[1]}" + ("/nt" if nt else "")
+
+
+def measured_traffic(tile, nt, scheme):
     """HBM bytes per launch from the committed PMC summary, only if it was
     taken on this kernel source and scheme, for this launch shape."""
     path = os.path.join(ROOT, "profiles", f"k_step_{scheme}_preform2048_traffic.json")
@@ -74,7 +78,7 @@ def measured_traffic(tile, scheme):
         return None
     if rec.get("kernel_src_sha256") != sha or rec.get("kernel") != KERNEL[scheme]:
         return None
-    t = rec.get("by_tile", {}).get(f"{tile[0]}x{tile[1]}")
+    t = rec.get("by_tile", {}).get(traffic_key(tile, nt))
     if t is None:
         return None
     return t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
@@ -219,6 +223,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--tile", type=str, default="auto", help="TXxSY or auto")
+    ap.add_argument("--load-hint", type=str, default="auto", choices=("auto", "0", "1"),
+                    help="with --tile: non-temporal load hint (auto keeps the default, 0)")
     ap.add_argument("--scheme", choices=("auto", "moments", "populations"), default="auto",
                     help="state between steps (auto: moments at tau = 1)")
     ap.add_argument("--compare-steps", type=int, default=1000,
@@ -265,9 +271,9 @@ def main():
         scheme = "moments" if float(p.tau) == 1.0 else "populations"
     stream = torch.cuda.Stream(device=dev)
 
-    def timed_run(scheme, steps, warmup, tile):
-        """Autotune (or set) the launch shape, warm up, time `steps` steps
-        with HIP events on the library's stream."""
+    def timed_run(scheme, steps, warmup, tile, hint="auto"):
+        """Autotune (or set) the launch shape and load hint, warm up, time
+        `steps` steps with HIP events on the library's stream."""
         sim = lbm.Sim.from_problem(prob, device=dev, stream=stream, scheme=scheme)
         if tile == "auto":
             (tx, sy), _ = sim.autotune(steps=50)
@@ -275,6 +281,9 @@ def main():
             tx, sy = (int(v) for v in tile.lower().split("x"))
             sim.set_tile(tx, sy)
             tx, sy = sim.tile()
+            if hint != "auto":
+                sim.set_load_hint(int(hint))
+        nt = sim.load_hint()
         sim.step(warmup)
         o0 = sim.observe()
         b0 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8), scheme)
@@ -292,11 +301,11 @@ def main():
         o1 = sim.observe()
         b1 = algorithmic_bytes(sim.fields(("solid",))["solid"].astype(np.uint8), scheme)
         del sim
-        return (tx, sy), ms, wall, o0, o1, b0, b1
+        return (tx, sy, nt), ms, wall, o0, o1, b0, b1
 
     with torch.cuda.stream(stream):
-        (tx, sy), ms, wall, o0, o1, bytes0, bytes1 = timed_run(scheme, args.steps, args.warmup,
-                                                              args.tile)
+        (tx, sy, nt), ms, wall, o0, o1, bytes0, bytes1 = timed_run(scheme, args.steps, args.warmup,
+                                                                  args.tile, args.load_hint)
         compare = None
         if args.compare_steps > 0:
             other = "populations" if scheme == "moments" else "moments"
@@ -304,7 +313,8 @@ def main():
                 ctile, cms, _, _, _, cb0, cb1 = timed_run(other, args.compare_steps, 20, "auto")
                 cstep = cms / args.compare_steps
                 cbytes = 0.5 * (cb0[0] + cb1[0])
-                compare = {"scheme": other, "kernel": KERNEL[other], "tile": list(ctile),
+                compare = {"scheme": other, "kernel": KERNEL[other], "tile": list(ctile[:2]),
+                           "load_hint": ctile[2],
                            "steps": args.compare_steps, "ms_per_step": round(cstep, 5),
                            "mlups": round(N / (cstep / 1e3) / 1e6, 1),
                            "bytes_per_lup": BYTES_PER_LUP[other],
@@ -316,7 +326,7 @@ def main():
     per_launch = 0.5 * (bytes0[0] + bytes1[0])
     fluid_only = 0.5 * (bytes0[1] + bytes1[1])
     achieved = per_launch / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic((tx, sy), scheme)
+    traffic = measured_traffic((tx, sy), nt, scheme)
     cons = abs(o1["solute"] + o1["precipitate"] + o1["solute_removed"] -
                (o0["solute"] + o0["precipitate"] + o0["solute_removed"]))
     out = {
@@ -336,7 +346,7 @@ def main():
                                f"{prob.solid_fraction:.3f}, reservoir 64 cols, D2Q5 D=0.05, "
                                "k_r=1e-3, threshold 1, 2-component Shan-Chen D2Q9 tau=1, "
                                f"FP32 state ({scheme}), FP64 arithmetic",
-                   "nx": p.nx, "ny": p.ny, "tile": [tx, sy], "scheme": scheme,
+                   "nx": p.nx, "ny": p.ny, "tile": [tx, sy], "load_hint": nt, "scheme": scheme,
                    "mflups_fluid": round(fluid0 * args.steps / (ms / 1e3) / 1e6, 1),
                    "wall_adjacent_nodes": bytes0[2],
                    "events_in_run": int(o1["n_events"] - o0["n_events"]),

@@ -194,6 +194,14 @@ lbm_status lbm_get_tile(const lbm_sim* sim, int32_t* tx, int32_t* sy);
  * traffic, so this costs no time and keeps FP32 rounding to the storage). */
 lbm_status lbm_set_arith(lbm_sim* sim, int32_t bits);
 
+/* Cache hint on the step's loads: 0 (default) the normal policy, 1 the
+ * non-temporal hint.  Which is faster depends on how the lattice's footprint
+ * meets the GPU's caches (on MI355X the hint gained 8% on a 2048^2 preform
+ * and lost 12-21% at 1448^2 and 4096^2), so lbm_autotune chooses it along with
+ * the launch shape.  It applies to the FP64 steps and changes no result bit. */
+lbm_status lbm_set_load_hint(lbm_sim* sim, int32_t nontemporal);
+lbm_status lbm_get_load_hint(const lbm_sim* sim, int32_t* nontemporal);
+
 /* State representation between steps (section "LB models": BGK relaxation
  * with relaxation time tau).  At tau = 1 a collision relaxes every
  * population fully onto the equilibrium of its component, so the
@@ -210,13 +218,14 @@ lbm_status lbm_set_arith(lbm_sim* sim, int32_t bits);
 enum { LBM_SCHEME_AUTO = 0, LBM_SCHEME_POPULATIONS = 1, LBM_SCHEME_MOMENTS = 2 };
 lbm_status lbm_set_scheme(lbm_sim* sim, int32_t scheme);
 
-/* Time the launch shapes (steps_per_candidate steps each, on a saved copy of
- * the state, which is restored), keep the fastest and report it.  When the
- * environment variable LBM_AUTOTUNE_CACHE names a file, a cached choice for
- * the same (GPU architecture, nx x ny, solute/reaction switches, arithmetic,
- * scheme)
- * is used without timing, and new choices are appended to it as JSON lines
- * {"key": ..., "tx": ..., "sy": ..., "ms": ...}. */
+/* Time the launch shapes and, with FP64 arithmetic, both load hints
+ * (steps_per_candidate steps each, on a saved copy of the state, which is
+ * restored), keep the fastest and report the shape (the hint is read with
+ * lbm_get_load_hint).  When the environment variable LBM_AUTOTUNE_CACHE names
+ * a file, a cached choice for the same (GPU architecture, nx x ny,
+ * solute/reaction switches, arithmetic, scheme) is used without timing, and
+ * new choices are appended to it as JSON lines
+ * {"key": ..., "tx": ..., "sy": ..., "ms": ..., "nt": ...}. */
 lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_candidate, int32_t* tx, int32_t* sy,
                         double* best_ms_per_step);
 

@@ -128,6 +128,7 @@ struct lbm_sim {
   long long step;  // current state index
   int tx, sy;
   int arith64;     // 1: FP64 arithmetic in the step (storage stays FP32)
+  int nt;          // 1: the step's loads carry the non-temporal cache hint
   int scheme;      // LBM_SCHEME_*
   bool mom;        // f[cur] holds moments of the last step, not populations
   bool poisoned;
@@ -229,7 +230,7 @@ lbm_status queue_steps(lbm_sim* s, long long n) {
     a.bit_p1 = pending_bit(s->step - 1);
     a.bit_p2 = pending_bit(s->step - 2);
     a.bit_cur = pending_bit(s->step);
-    hipError_t e = launch_step(a, s->tx, s->arith64, kind, s->stream);
+    hipError_t e = launch_step(a, s->tx, s->arith64, kind, s->nt, s->stream);
     if (e != hipSuccess) {
       s->poisoned = true;
       return fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
@@ -345,6 +346,7 @@ lbm_status lbm_init(const lbm_params* p, const uint8_t* solid, const double* rho
   s->step = 0;
   default_tile(*p, &s->tx, &s->sy);
   s->arith64 = 1;
+  s->nt = 0;
   s->scheme = LBM_SCHEME_AUTO;
   s->mom = false;
   // stage the FP64 inputs in the second population buffer (72 B per node)
@@ -585,6 +587,19 @@ lbm_status lbm_set_arith(lbm_sim* s, int32_t bits) {
   return LBM_OK;
 }
 
+lbm_status lbm_set_load_hint(lbm_sim* s, int32_t nontemporal) {
+  if (!s) return fail(LBM_EINVAL, "handle is NULL");
+  if (nontemporal != 0 && nontemporal != 1) return fail(LBM_EINVAL, "load hint must be 0 or 1");
+  s->nt = nontemporal;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_load_hint(const lbm_sim* s, int32_t* nontemporal) {
+  if (!s || !nontemporal) return fail(LBM_EINVAL, "NULL argument");
+  *nontemporal = s->nt;
+  return LBM_OK;
+}
+
 lbm_status lbm_get_tile(const lbm_sim* s, int32_t* tx, int32_t* sy) {
   if (!s || !tx || !sy) return fail(LBM_EINVAL, "NULL argument");
   *tx = use_moments(s->scheme, s->p) ? 64 : s->tx;  // moment step: 64-lane tiles
@@ -597,7 +612,8 @@ lbm_status lbm_get_tile(const lbm_sim* s, int32_t* tx, int32_t* sy) {
 namespace {
 
 // Autotune cache: a JSON-lines file named by LBM_AUTOTUNE_CACHE, one object
-// per line {"key": "<arch>:<nx>x<ny>:<flags>:<arith>:<scheme>", "tx": .., "sy": .., "ms": ..}.
+// per line {"key": "<arch>:<nx>x<ny>:<flags>:<arith>:<scheme>", "tx": .., "sy": .., "ms": ..,
+// "nt": ..} (a line without "nt" means the default load policy).
 std::string tune_key(const lbm_sim* s) {
   hipDeviceProp_t prop{};
   int dev = 0;
@@ -614,7 +630,7 @@ std::string tune_key(const lbm_sim* s) {
   return buf;
 }
 
-bool tune_lookup(const std::string& key, int* tx, int* sy, double* ms) {
+bool tune_lookup(const std::string& key, int* tx, int* sy, double* ms, int* nt) {
   const char* path = getenv("LBM_AUTOTUNE_CACHE");
   if (!path || !*path) return false;
   FILE* fh = fopen(path, "r");
@@ -626,7 +642,10 @@ bool tune_lookup(const std::string& key, int* tx, int* sy, double* ms) {
     double m = 0;
     if (sscanf(line, " {\"key\": \"%255[^\"]\", \"tx\": %d, \"sy\": %d, \"ms\": %lf", k, &a, &b, &m) == 4 &&
         key == k && tile_ok(a, b)) {
-      *tx = a; *sy = b; *ms = m;
+      int h = 0;
+      const char* q = strstr(line, "\"nt\":");
+      if (q && (sscanf(q, "\"nt\": %d", &h) != 1 || (h != 0 && h != 1))) continue;
+      *tx = a; *sy = b; *ms = m; *nt = h;
       found = true;  // the last entry for a key wins
     }
   }
@@ -634,12 +653,13 @@ bool tune_lookup(const std::string& key, int* tx, int* sy, double* ms) {
   return found;
 }
 
-void tune_store(const std::string& key, int tx, int sy, double ms) {
+void tune_store(const std::string& key, int tx, int sy, double ms, int nt) {
   const char* path = getenv("LBM_AUTOTUNE_CACHE");
   if (!path || !*path) return;
   FILE* fh = fopen(path, "a");
   if (!fh) return;
-  fprintf(fh, "{\"key\": \"%s\", \"tx\": %d, \"sy\": %d, \"ms\": %.6f}\n", key.c_str(), tx, sy, ms);
+  fprintf(fh, "{\"key\": \"%s\", \"tx\": %d, \"sy\": %d, \"ms\": %.6f, \"nt\": %d}\n", key.c_str(), tx,
+          sy, ms, nt);
   fclose(fh);
 }
 
@@ -652,11 +672,12 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   if (st != LBM_OK) return st;
   if (steps < 1) return fail(LBM_EINVAL, "steps_per_candidate must be >= 1");
   {
-    int ctx = 0, csy = 0;
+    int ctx = 0, csy = 0, cnt = 0;
     double cms = 0;
-    if (tune_lookup(tune_key(s), &ctx, &csy, &cms)) {
+    if (tune_lookup(tune_key(s), &ctx, &csy, &cms, &cnt)) {
       s->tx = ctx;
       s->sy = csy;
+      s->nt = cnt;
       if (tx_out) *tx_out = ctx;
       if (sy_out) *sy_out = csy;
       if (best_ms) *best_ms = cms;
@@ -673,8 +694,10 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   HIPCHECK(hipEventCreate(&e1));
   const int txs[] = {64, 128, 256};
   const int sys[] = {6, 8, 9, 10, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128};
-  int btx = s->tx, bsy = s->sy;
+  int btx = s->tx, bsy = s->sy, bnt = s->nt;
   float best = 1e30f;
+  // the load hint only changes the FP64 steps
+  for (int nt = 0; nt < (s->arith64 ? 2 : 1) && st == LBM_OK; ++nt)
   for (int tx : txs) {
     if (use_moments(s->scheme, s->p) && tx != 64) continue;  // 64-lane tiles only
     if (tx > 2 * s->p.nx + 2 && tx != 64) continue;
@@ -682,6 +705,7 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
       if (sy > 2 * s->p.ny && sy != 8) continue;
       s->tx = tx;
       s->sy = sy;
+      s->nt = nt;
       if ((st = queue_steps(s, 2)) != LBM_OK) break;
       if (hipEventRecord(e0, s->stream) != hipSuccess) { st = fail(LBM_EDEVICE, "autotune event"); break; }
       if ((st = queue_steps(s, steps)) != LBM_OK) break;
@@ -691,7 +715,7 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
         st = fail(LBM_EDEVICE, "autotune timing");
         break;
       }
-      if (ms < best) { best = ms; btx = tx; bsy = sy; }
+      if (ms < best) { best = ms; btx = tx; bsy = sy; bnt = nt; }
     }
     if (st != LBM_OK) break;
   }
@@ -701,7 +725,8 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   if ((st = lbm_load(s, blob.data(), n)) != LBM_OK) return st;
   s->tx = btx;
   s->sy = bsy;
-  tune_store(tune_key(s), btx, bsy, best / steps);
+  s->nt = bnt;
+  tune_store(tune_key(s), btx, bsy, best / steps, bnt);
   if (tx_out) *tx_out = btx;
   if (sy_out) *sy_out = bsy;
   if (best_ms) *best_ms = best / steps;

@@ -67,7 +67,8 @@ enum StepKind { KIND_POP = 0, KIND_PM = 1, KIND_MM = 2 };
 // Records a message for lbm_last_error() and returns s.
 lbm_status fail(lbm_status s, const char* fmt, ...);
 
-hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, hipStream_t st);
+// nt: non-temporal load hint (FP64 moment and population steps)
+hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, int nt, hipStream_t st);
 // var: some instance uses a reaction or solute-lattice variant
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
                              const long long* stepc, int tx, int solute, int react, int var,

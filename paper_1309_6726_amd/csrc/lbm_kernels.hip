@@ -566,11 +566,11 @@ __device__ __forceinline__ R feq_m(R wr, R c, R eu) {
 // iteration's memory latency.  The summation order of every node is fixed,
 // so results do not depend on the tile shape.
 //
-// NT: the copies carry the non-temporal cache hint.  On a single large
-// lattice every byte is read once per step and the hint made the step ~6%
-// faster; on a batch of narrow channels, whose halo rows are a large share
-// and are re-read from L2, it made it ~14% slower, so the batched step
-// leaves it off.
+// NT: the copies carry the non-temporal cache hint.  Whether it pays depends
+// on how the step's footprint meets the caches: on the 2048x2048 preform it
+// made the step ~8% faster, at 1448^2 and 4096^2 12-21% slower, and on a
+// batch of narrow channels 14% slower.  The single-lattice step therefore
+// takes it as an autotuned choice; the batched step leaves it off.
 template <bool SOLUTE, bool REACT, bool VAR, typename R, bool NT>
 __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) {
   constexpr int CPOL = NT ? CPOL_NT : 0;
@@ -882,14 +882,14 @@ __device__ __forceinline__ void run_tile(const StepArgs& a, int strip, int seg, 
     step_tile<SOLUTE, REACT, VAR, R, KIND == KIND_PM, NT>(a, strip, seg, lds_raw);
 }
 
-template <bool SOLUTE, bool REACT, bool VAR, typename R, int KIND>
+template <bool SOLUTE, bool REACT, bool VAR, typename R, int KIND, bool NT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_step(const StepArgs a) {
   extern __shared__ char lds_raw[];
   const int T = a.nstrips * a.nsegs;
   const int tile = a.remap ? xcd_tile(blockIdx.x, T) : (int)blockIdx.x;
   const int seg = tile / a.nstrips;
-  run_tile<SOLUTE, REACT, VAR, R, KIND, true>(a, tile - seg * a.nstrips, seg, lds_raw);
+  run_tile<SOLUTE, REACT, VAR, R, KIND, NT>(a, tile - seg * a.nstrips, seg, lds_raw);
 }
 
 // Batched step: one launch advances every instance of a batch by one step.
@@ -1329,32 +1329,40 @@ size_t step_lds_bytes(int kind, int tx, int arith64) {
 // instruction stream.
 inline bool uses_variants(const StepArgs& a) { return a.c_eq > 0.0 || a.hold_x > 0 || a.q4; }
 
-template <typename R, int KIND>
+template <typename R, int KIND, bool NT>
 void launch_step_t(const StepArgs& a, int T, int tx, size_t lds, hipStream_t st) {
   if (a.solute && a.react && uses_variants(a))
-    hipLaunchKernelGGL((k_step<true, true, true, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+    hipLaunchKernelGGL((k_step<true, true, true, R, KIND, NT>), dim3(T), dim3(tx), lds, st, a);
   else if (a.solute && a.react)
-    hipLaunchKernelGGL((k_step<true, true, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+    hipLaunchKernelGGL((k_step<true, true, false, R, KIND, NT>), dim3(T), dim3(tx), lds, st, a);
   else if (a.solute && uses_variants(a))
-    hipLaunchKernelGGL((k_step<true, false, true, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+    hipLaunchKernelGGL((k_step<true, false, true, R, KIND, NT>), dim3(T), dim3(tx), lds, st, a);
   else if (a.solute)
-    hipLaunchKernelGGL((k_step<true, false, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+    hipLaunchKernelGGL((k_step<true, false, false, R, KIND, NT>), dim3(T), dim3(tx), lds, st, a);
   else
-    hipLaunchKernelGGL((k_step<false, false, false, R, KIND>), dim3(T), dim3(tx), lds, st, a);
+    hipLaunchKernelGGL((k_step<false, false, false, R, KIND, NT>), dim3(T), dim3(tx), lds, st, a);
 }
 
-hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, hipStream_t st) {
+// nt: the non-temporal load hint, compiled for the FP64 moment and
+// population steps only (the one-off PM step and FP32 arithmetic ignore it).
+hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, int nt, hipStream_t st) {
   const int T = a.nstrips * a.nsegs;
   if (kind == KIND_MM) tx = 64;  // the moment step runs one wavefront per tile
   const size_t lds = step_lds_bytes(kind, tx, arith64);
   if (arith64) {
-    if (kind == KIND_MM) launch_step_t<double, KIND_MM>(a, T, tx, lds, st);
-    else if (kind == KIND_PM) launch_step_t<double, KIND_PM>(a, T, tx, lds, st);
-    else launch_step_t<double, KIND_POP>(a, T, tx, lds, st);
+    if (kind == KIND_MM) {
+      if (nt) launch_step_t<double, KIND_MM, true>(a, T, tx, lds, st);
+      else launch_step_t<double, KIND_MM, false>(a, T, tx, lds, st);
+    } else if (kind == KIND_PM) {
+      launch_step_t<double, KIND_PM, false>(a, T, tx, lds, st);
+    } else {
+      if (nt) launch_step_t<double, KIND_POP, true>(a, T, tx, lds, st);
+      else launch_step_t<double, KIND_POP, false>(a, T, tx, lds, st);
+    }
   } else {
-    if (kind == KIND_MM) launch_step_t<float, KIND_MM>(a, T, tx, lds, st);
-    else if (kind == KIND_PM) launch_step_t<float, KIND_PM>(a, T, tx, lds, st);
-    else launch_step_t<float, KIND_POP>(a, T, tx, lds, st);
+    if (kind == KIND_MM) launch_step_t<float, KIND_MM, false>(a, T, tx, lds, st);
+    else if (kind == KIND_PM) launch_step_t<float, KIND_PM, false>(a, T, tx, lds, st);
+    else launch_step_t<float, KIND_POP, false>(a, T, tx, lds, st);
   }
   return hipGetLastError();
 }

@@ -25,7 +25,8 @@ SCHEMES = {"auto": 0, "populations": 1, "moments": 2}
 
 EXPORTS = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe", "lbm_fields",
            "lbm_events", "lbm_save", "lbm_load", "lbm_set_tile", "lbm_get_tile",
-           "lbm_autotune", "lbm_set_arith", "lbm_set_scheme", "lbm_destroy", "lbm_strerror", "lbm_last_error",
+           "lbm_autotune", "lbm_set_arith", "lbm_set_load_hint", "lbm_get_load_hint",
+           "lbm_set_scheme", "lbm_destroy", "lbm_strerror", "lbm_last_error",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_set_tile",
            "lbm_batch_get_tile", "lbm_batch_set_scheme", "lbm_batch_set_graph", "lbm_batch_step",
            "lbm_batch_record_fronts", "lbm_batch_fronts", "lbm_batch_observe",
@@ -105,6 +106,8 @@ def lib():
             "lbm_load": [P, P, C.c_size_t],
             "lbm_set_tile": [P, C.c_int32, C.c_int32],
             "lbm_set_arith": [P, C.c_int32],
+            "lbm_set_load_hint": [P, C.c_int32],
+            "lbm_get_load_hint": [P, C.POINTER(C.c_int32)],
             "lbm_set_scheme": [P, C.c_int32],
             "lbm_batch_set_scheme": [P, C.c_int32],
             "lbm_get_tile": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
@@ -258,6 +261,15 @@ class Sim:
 
     def set_arith(self, bits: int):
         check(lib().lbm_set_arith(self.h, int(bits)))
+
+    def set_load_hint(self, nontemporal: int):
+        """0: normal cache policy on the step's loads, 1: non-temporal."""
+        check(lib().lbm_set_load_hint(self.h, int(nontemporal)))
+
+    def load_hint(self) -> int:
+        v = C.c_int32(0)
+        check(lib().lbm_get_load_hint(self.h, C.byref(v)))
+        return v.value
 
     def set_scheme(self, scheme: str):
         """'auto' (moments at tau = 1), 'populations' or 'moments'."""

@@ -233,6 +233,27 @@ def test_tile_shapes_bitwise_sweep_geometry(lbm, scheme):
             assert state == ref[0], tile
 
 
+@pytest.mark.parametrize("scheme", ["moments", "populations"])
+def test_load_hint_changes_no_bit(lbm, scheme):
+    """The non-temporal load hint is a cache policy: same state and events."""
+    prob = inputs.capillary_problem(300, 40, 20, seed=5, k_r=0.01, threshold=0.4, D=0.05)
+    ref = None
+    for nt in (0, 1):
+        PT.say(f"[load hint] {scheme} nt={nt}")
+        sim = lbm.Sim.from_problem(prob, tile=(64, 12), scheme=scheme)
+        sim.set_load_hint(nt)
+        sim.step(700)
+        blob = sim.save()
+        ev = sorted(PT.event_set(sim.events()))
+        n_ev = int(np.frombuffer(blob[32:40], dtype=np.int64)[0])
+        state = blob[:len(blob) - n_ev * lbm.EVENT_DTYPE.itemsize]
+        if ref is None:
+            ref = (state, ev)
+            assert len(ev) > 0
+        else:
+            assert ev == ref[1] and state == ref[0], scheme
+
+
 def test_schemes_agree(lbm, oracle_mod):
     """tau = 1: populations and moments between steps give the same run to
     FP32 rounding: fields, masses, fronts and the exact growth events."""
@@ -429,6 +450,8 @@ def test_error_paths(lbm):
     with pytest.raises(L.LbmError):
         sim.set_tile(96, 8)
     with pytest.raises(L.LbmError):
+        sim.set_load_hint(2)
+    with pytest.raises(L.LbmError):
         sim.step(-1)
     # NaN written into the population state -> observe reports and poisons
     sim.step(10)
@@ -458,12 +481,15 @@ def test_autotune_cache(lbm, tmp_path, monkeypatch):
     PT.say("[autotune cache]")
     a = lbm.Sim.from_problem(prob)
     (tx, sy), ms = a.autotune(steps=2)
+    nt = a.load_hint()
+    assert nt in (0, 1)
     lines = path.read_text().splitlines()
-    assert len(lines) == 1 and f'"tx": {tx}, "sy": {sy}' in lines[0]
+    assert len(lines) == 1 and f'"tx": {tx}, "sy": {sy}' in lines[0] and f'"nt": {nt}' in lines[0]
     b = lbm.Sim.from_problem(prob)
+    b.set_load_hint(1 - nt)
     assert b.autotune(steps=2)[0] == (tx, sy)
     assert len(path.read_text().splitlines()) == 1
-    assert b.tile() == (tx, sy)
+    assert b.tile() == (tx, sy) and b.load_hint() == nt
 
 
 @pytest.mark.parametrize("scheme", ["moments", "populations"])
