@@ -697,27 +697,28 @@ lbm_status lbm_autotune(lbm_sim* s, int32_t steps, int32_t* tx_out, int32_t* sy_
   int btx = s->tx, bsy = s->sy, bnt = s->nt;
   float best = 1e30f;
   // the load hint only changes the FP64 steps
-  for (int nt = 0; nt < (s->arith64 ? 2 : 1) && st == LBM_OK; ++nt)
-  for (int tx : txs) {
-    if (use_moments(s->scheme, s->p) && tx != 64) continue;  // 64-lane tiles only
-    if (tx > 2 * s->p.nx + 2 && tx != 64) continue;
-    for (int sy : sys) {
-      if (sy > 2 * s->p.ny && sy != 8) continue;
-      s->tx = tx;
-      s->sy = sy;
-      s->nt = nt;
-      if ((st = queue_steps(s, 2)) != LBM_OK) break;
-      if (hipEventRecord(e0, s->stream) != hipSuccess) { st = fail(LBM_EDEVICE, "autotune event"); break; }
-      if ((st = queue_steps(s, steps)) != LBM_OK) break;
-      float ms = 0;
-      if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = fail(LBM_EDEVICE, "autotune timing");
-        break;
+  for (int nt = 0; nt < (s->arith64 ? 2 : 1) && st == LBM_OK; ++nt) {
+    for (int tx : txs) {
+      if (use_moments(s->scheme, s->p) && tx != 64) continue;  // 64-lane tiles only
+      if (tx > 2 * s->p.nx + 2 && tx != 64) continue;
+      for (int sy : sys) {
+        if (sy > 2 * s->p.ny && sy != 8) continue;
+        s->tx = tx;
+        s->sy = sy;
+        s->nt = nt;
+        if ((st = queue_steps(s, 2)) != LBM_OK) break;
+        if (hipEventRecord(e0, s->stream) != hipSuccess) { st = fail(LBM_EDEVICE, "autotune event"); break; }
+        if ((st = queue_steps(s, steps)) != LBM_OK) break;
+        float ms = 0;
+        if (hipEventRecord(e1, s->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = fail(LBM_EDEVICE, "autotune timing");
+          break;
+        }
+        if (ms < best) { best = ms; btx = tx; bsy = sy; bnt = nt; }
       }
-      if (ms < best) { best = ms; btx = tx; bsy = sy; bnt = nt; }
+      if (st != LBM_OK) break;
     }
-    if (st != LBM_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
