@@ -43,11 +43,13 @@ def _tiled(prob):
     return inputs.Problem(p, t(prob.solid), t(prob.rho1), t(prob.rho2), t(prob.conc))
 
 
-@pytest.mark.parametrize("scheme,tile", [("moments", (64, 9)), ("populations", (256, 40))])
-def test_max_lattice_is_periodic_copies_of_small(lbm, scheme, tile):
+@pytest.mark.parametrize("scheme,tile,hint", [("moments", (64, 9), 0), ("moments", (64, 12), 1),
+                                              ("populations", (256, 40), 1)])
+def test_max_lattice_is_periodic_copies_of_small(lbm, scheme, tile, hint):
     small = _small()
-    PT.say(f"[max size] small {NX_S}x{NY_S} {scheme} {tile}: {STEPS} steps")
+    PT.say(f"[max size] small {NX_S}x{NY_S} {scheme} {tile} hint {hint}: {STEPS} steps")
     s = lbm.Sim.from_problem(small, tile=tile, scheme=scheme)
+    s.set_load_hint(hint)
     s.step(STEPS)
     fs = s.fields()
     ev_s = s.events()
@@ -58,6 +60,7 @@ def test_max_lattice_is_periodic_copies_of_small(lbm, scheme, tile):
     nx, ny = big.params.nx, big.params.ny
     PT.say(f"[max size] tiled {nx}x{ny} ({nx * ny} nodes) {scheme} {tile}: {STEPS} steps")
     b = lbm.Sim.from_problem(big, tile=tile, scheme=scheme)
+    b.set_load_hint(hint)
     del big
     b.step(STEPS)
     for name, small_field in fs.items():
