@@ -188,12 +188,6 @@ lbm_status lbm_load(lbm_sim* sim, const void* blob, size_t n);
 lbm_status lbm_set_tile(lbm_sim* sim, int32_t tx, int32_t sy);
 lbm_status lbm_get_tile(const lbm_sim* sim, int32_t* tx, int32_t* sy);
 
-/* Arithmetic precision of the step: 64 (default) or 32 bits.  Populations
- * are stored as FP32 either way; 64 computes moments, forces and the
- * collision in FP64 from the stored values (the step is bound by memory
- * traffic, so this costs no time and keeps FP32 rounding to the storage). */
-lbm_status lbm_set_arith(lbm_sim* sim, int32_t bits);
-
 /* Cache hint on the step's loads: 0 (default) the normal policy, 1 the
  * non-temporal hint.  Which is faster depends on how the lattice's footprint
  * meets the GPU's caches (on MI355X the hint gained 8% on a 2048^2 preform
@@ -290,9 +284,10 @@ void lbm_batch_destroy(lbm_batch* b);
 /* ------------------------------------------------------------------------
  * Learned surrogate of the sweep: an MLP 5 -> 256 -> 256 -> 256 -> 65 (ReLU)
  * mapping capillary width W, length L, reaction rate k_r, contact angle
- * (degrees) and precipitation threshold to the centreline front z(t_j)/L at
- * the 64 sample times t_j = ceil(j T / 64) and the pore-closure time / T (1 if
- * no closure within T).  Inputs are normalised inside the library to [-1, 1]
+ * (degrees) and precipitation threshold to 65 outputs, which the sweep
+ * pipeline trains as the centreline front z(t_j) at the 64 sample times
+ * t_j = ceil(j T / 64), divided by a Washburn travel scale, and the
+ * pore-closure time / T (1 if no closure within T).  Inputs are normalised inside the library to [-1, 1]
  * over the box [lo, hi] (log10 for k_r).  Dense layers run on the matrix cores
  * (BF16 operands, FP32 accumulation) in forward and backward; training keeps
  * FP32 master weights and uses Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the

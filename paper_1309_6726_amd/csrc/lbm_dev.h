@@ -67,12 +67,15 @@ enum StepKind { KIND_POP = 0, KIND_PM = 1, KIND_MM = 2 };
 // Records a message for lbm_last_error() and returns s.
 lbm_status fail(lbm_status s, const char* fmt, ...);
 
-// nt: non-temporal load hint (FP64 moment and population steps)
-hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, int nt, hipStream_t st);
+// nt: non-temporal load hint (moment and population steps)
+hipError_t launch_step(const StepArgs& a, int tx, int kind, int nt, hipStream_t st);
 // var: some instance uses a reaction or solute-lattice variant
+// One batched step at index *stepc + j; a sequence of n such launches
+// (j = 0..n-1) is followed by launch_tick(stepc, n).
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
-                             const long long* stepc, int tx, int solute, int react, int var,
-                             int arith64, int kind, hipStream_t st);
+                             const long long* stepc, int j, int tx, int solute, int react,
+                             int var, int kind, hipStream_t st);
+hipError_t launch_tick(long long* stepc, int n, hipStream_t st);
 hipError_t launch_front_batch(const StepArgs* insts, const int4* capi, const long long* stepc,
                               int n, int slot, int nslots, int mom, double* table, hipStream_t st);
 // Populations of state n rebuilt from stored moments (zero at nodes solid in
@@ -92,7 +95,7 @@ hipError_t launch_observe(const float* f, const float* g, const uint8_t* mask, c
                           hipStream_t st);
 hipError_t launch_fields(const float* f, const float* g, const uint8_t* mask, const double* m,
                          int nx, int ny, long long P, unsigned p1, unsigned p2, int mom,
-                         int solute, int react, float G, float Gads1, float Gads2, float ax,
-                         float ay, double* out, hipStream_t st);
+                         int solute, int react, double G, double Gads1, double Gads2, double ax,
+                         double ay, double* out, hipStream_t st);
 
 }  // namespace lbmdev

@@ -895,14 +895,16 @@ k_step(const StepArgs a) {
 // Batched step: one launch advances every instance of a batch by one step.
 // Block b takes tile tiles[b] (instance, strip, segment; the host orders the
 // list per XCD); the instance's arguments for the current parity come from
-// device memory, and the step index from the device counter, so a sequence of
-// launches can be captured once in a graph and replayed.
+// device memory, and the step index is the device counter *stepc plus the
+// launch's offset j within its sequence.  A sequence of n launches (offsets
+// 0..n-1) is followed by k_tick(stepc, n), so a captured sequence replays
+// from where the last one ended.
 template <bool SOLUTE, bool REACT, bool VAR, typename R, int KIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_step_batch(const StepArgs* __restrict__ insts, const int4* __restrict__ tiles,
-             const long long* __restrict__ stepc) {
+             const long long* __restrict__ stepc, int j) {
   extern __shared__ char lds_raw[];
-  const long long step = *stepc;
+  const long long step = *stepc + j;
   const int4 e = tiles[blockIdx.x];
   StepArgs a = insts[2 * e.x + (int)(step & 1)];
   a.step = step;
@@ -912,9 +914,9 @@ k_step_batch(const StepArgs* __restrict__ insts, const int4* __restrict__ tiles,
   run_tile<SOLUTE, REACT, VAR, R, KIND, false>(a, e.y, e.z, lds_raw);
 }
 
-// Advances the device step counter (a vector atomic, one lane).
-__global__ void k_tick(long long* stepc) {
-  if (threadIdx.x == 0) atomicAdd((unsigned long long*)stepc, 1ull);
+// Advances the device step counter by n (one lane).
+__global__ void k_tick(long long* stepc, int n) {
+  if (threadIdx.x == 0) *stepc += n;
 }
 
 // Rest-state populations from the FP64 densities (rounded once to FP32).
@@ -1253,8 +1255,8 @@ __global__ void __launch_bounds__(256) k_front_batch(const StepArgs* __restrict_
 template <typename Src>
 __global__ void k_fields(Src src, const float* __restrict__ g, const uint8_t* __restrict__ mask,
                          const double* __restrict__ m, int nx, int ny, long long P, unsigned sb,
-                         int solute, int react, float G, float Gads1, float Gads2, float ax,
-                         float ay, double* __restrict__ out) {
+                         int solute, int react, double G, double Gads1, double Gads2, double ax,
+                         double ay, double* __restrict__ out) {
   const long long N = (long long)nx * ny;
   const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -1318,10 +1320,9 @@ __global__ void k_unpack(MomSrc src, float* __restrict__ fout) {
 }
 
 // ---- launchers ------------------------------------------------------------
-size_t step_lds_bytes(int kind, int tx, int arith64) {
-  const size_t r = arith64 ? sizeof(double) : sizeof(float);
+size_t step_lds_bytes(int kind, int tx) {
   if (kind == KIND_MM) return 0;  // registers and cross-lane moves only
-  return (size_t)4 * tx * (2 * r + sizeof(float));
+  return (size_t)4 * tx * (2 * sizeof(double) + sizeof(float));
 }
 
 // Runs that use a reaction or solute-lattice variant (saturation, held
@@ -1343,60 +1344,52 @@ void launch_step_t(const StepArgs& a, int T, int tx, size_t lds, hipStream_t st)
     hipLaunchKernelGGL((k_step<false, false, false, R, KIND, NT>), dim3(T), dim3(tx), lds, st, a);
 }
 
-// nt: the non-temporal load hint, compiled for the FP64 moment and
-// population steps only (the one-off PM step and FP32 arithmetic ignore it).
-hipError_t launch_step(const StepArgs& a, int tx, int arith64, int kind, int nt, hipStream_t st) {
+// nt: the non-temporal load hint, compiled for the moment and population
+// steps (the one-off PM step ignores it).  The arithmetic is FP64 throughout.
+hipError_t launch_step(const StepArgs& a, int tx, int kind, int nt, hipStream_t st) {
   const int T = a.nstrips * a.nsegs;
   if (kind == KIND_MM) tx = 64;  // the moment step runs one wavefront per tile
-  const size_t lds = step_lds_bytes(kind, tx, arith64);
-  if (arith64) {
-    if (kind == KIND_MM) {
-      if (nt) launch_step_t<double, KIND_MM, true>(a, T, tx, lds, st);
-      else launch_step_t<double, KIND_MM, false>(a, T, tx, lds, st);
-    } else if (kind == KIND_PM) {
-      launch_step_t<double, KIND_PM, false>(a, T, tx, lds, st);
-    } else {
-      if (nt) launch_step_t<double, KIND_POP, true>(a, T, tx, lds, st);
-      else launch_step_t<double, KIND_POP, false>(a, T, tx, lds, st);
-    }
+  const size_t lds = step_lds_bytes(kind, tx);
+  if (kind == KIND_MM) {
+    if (nt) launch_step_t<double, KIND_MM, true>(a, T, tx, lds, st);
+    else launch_step_t<double, KIND_MM, false>(a, T, tx, lds, st);
+  } else if (kind == KIND_PM) {
+    launch_step_t<double, KIND_PM, false>(a, T, tx, lds, st);
   } else {
-    if (kind == KIND_MM) launch_step_t<float, KIND_MM, false>(a, T, tx, lds, st);
-    else if (kind == KIND_PM) launch_step_t<float, KIND_PM, false>(a, T, tx, lds, st);
-    else launch_step_t<float, KIND_POP, false>(a, T, tx, lds, st);
+    if (nt) launch_step_t<double, KIND_POP, true>(a, T, tx, lds, st);
+    else launch_step_t<double, KIND_POP, false>(a, T, tx, lds, st);
   }
   return hipGetLastError();
 }
 
 template <typename R, int KIND>
 void launch_batch_t(const StepArgs* insts, const int4* tiles, int ntiles, const long long* stepc,
-                    int tx, int solute, int react, int var, size_t lds, hipStream_t st) {
+                    int j, int tx, int solute, int react, int var, size_t lds, hipStream_t st) {
   if (solute && react && var)
-    hipLaunchKernelGGL((k_step_batch<true, true, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    hipLaunchKernelGGL((k_step_batch<true, true, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc, j);
   else if (solute && react)
-    hipLaunchKernelGGL((k_step_batch<true, true, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    hipLaunchKernelGGL((k_step_batch<true, true, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc, j);
   else if (solute && var)
-    hipLaunchKernelGGL((k_step_batch<true, false, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    hipLaunchKernelGGL((k_step_batch<true, false, true, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc, j);
   else if (solute)
-    hipLaunchKernelGGL((k_step_batch<true, false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    hipLaunchKernelGGL((k_step_batch<true, false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc, j);
   else
-    hipLaunchKernelGGL((k_step_batch<false, false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc);
+    hipLaunchKernelGGL((k_step_batch<false, false, false, R, KIND>), dim3(ntiles), dim3(tx), lds, st, insts, tiles, stepc, j);
 }
 
 hipError_t launch_step_batch(const StepArgs* insts, const int4* tiles, int ntiles,
-                             const long long* stepc, int tx, int solute, int react, int var,
-                             int arith64, int kind, hipStream_t st) {
+                             const long long* stepc, int j, int tx, int solute, int react,
+                             int var, int kind, hipStream_t st) {
   if (kind == KIND_MM) tx = 64;
-  const size_t lds = step_lds_bytes(kind, tx, arith64);
-  if (arith64) {
-    if (kind == KIND_MM) launch_batch_t<double, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
-    else if (kind == KIND_PM) launch_batch_t<double, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
-    else launch_batch_t<double, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
-  } else {
-    if (kind == KIND_MM) launch_batch_t<float, KIND_MM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
-    else if (kind == KIND_PM) launch_batch_t<float, KIND_PM>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
-    else launch_batch_t<float, KIND_POP>(insts, tiles, ntiles, stepc, tx, solute, react, var, lds, st);
-  }
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, (long long*)stepc);
+  const size_t lds = step_lds_bytes(kind, tx);
+  if (kind == KIND_MM) launch_batch_t<double, KIND_MM>(insts, tiles, ntiles, stepc, j, tx, solute, react, var, lds, st);
+  else if (kind == KIND_PM) launch_batch_t<double, KIND_PM>(insts, tiles, ntiles, stepc, j, tx, solute, react, var, lds, st);
+  else launch_batch_t<double, KIND_POP>(insts, tiles, ntiles, stepc, j, tx, solute, react, var, lds, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick(long long* stepc, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, stepc, n);
   return hipGetLastError();
 }
 
@@ -1456,8 +1449,8 @@ hipError_t launch_observe(const float* f, const float* g, const uint8_t* mask, c
 
 hipError_t launch_fields(const float* f, const float* g, const uint8_t* mask, const double* m,
                          int nx, int ny, long long P, unsigned p1, unsigned p2, int mom,
-                         int solute, int react, float G, float Gads1, float Gads2, float ax,
-                         float ay, double* out, hipStream_t st) {
+                         int solute, int react, double G, double Gads1, double Gads2, double ax,
+                         double ay, double* out, hipStream_t st) {
   const int blocks = grid_for((long long)nx * ny);
   const unsigned sb = 1u | p1 | p2;
   if (mom)

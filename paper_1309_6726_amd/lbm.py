@@ -25,7 +25,7 @@ SCHEMES = {"auto": 0, "populations": 1, "moments": 2}
 
 EXPORTS = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe", "lbm_fields",
            "lbm_events", "lbm_save", "lbm_load", "lbm_set_tile", "lbm_get_tile",
-           "lbm_autotune", "lbm_set_arith", "lbm_set_load_hint", "lbm_get_load_hint",
+           "lbm_autotune", "lbm_set_load_hint", "lbm_get_load_hint",
            "lbm_set_scheme", "lbm_destroy", "lbm_strerror", "lbm_last_error",
            "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_set_tile",
            "lbm_batch_get_tile", "lbm_batch_set_scheme", "lbm_batch_set_graph", "lbm_batch_step",
@@ -105,7 +105,6 @@ def lib():
             "lbm_save": [P, P, C.c_size_t, C.POINTER(C.c_size_t)],
             "lbm_load": [P, P, C.c_size_t],
             "lbm_set_tile": [P, C.c_int32, C.c_int32],
-            "lbm_set_arith": [P, C.c_int32],
             "lbm_set_load_hint": [P, C.c_int32],
             "lbm_get_load_hint": [P, C.POINTER(C.c_int32)],
             "lbm_set_scheme": [P, C.c_int32],
@@ -177,7 +176,7 @@ class Sim:
     workspace is a torch uint8 tensor owned by this object."""
 
     def __init__(self, p, solid, rho1, rho2, conc=None, *, device="cuda:0", stream=None,
-                 tile=None, arith=None, scheme=None):
+                 tile=None, scheme=None):
         import torch
         self.p = p
         self.nx, self.ny = int(p.nx), int(p.ny)
@@ -201,8 +200,6 @@ class Sim:
         self.h = h
         if tile is not None:
             self.set_tile(*tile)
-        if arith is not None:
-            self.set_arith(arith)
         if scheme is not None:
             self.set_scheme(scheme)
 
@@ -258,9 +255,6 @@ class Sim:
 
     def set_tile(self, tx: int, sy: int):
         check(lib().lbm_set_tile(self.h, int(tx), int(sy)))
-
-    def set_arith(self, bits: int):
-        check(lib().lbm_set_arith(self.h, int(bits)))
 
     def set_load_hint(self, nontemporal: int):
         """0: normal cache policy on the step's loads, 1: non-temporal."""

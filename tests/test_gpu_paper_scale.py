@@ -121,3 +121,55 @@ def test_radii_order_and_shrink(runs):
         assert rave[-1] < rave[0] and rh[-1] < rh[0] and rmin[-1] < rmin[0]
         r0 = out[((L, H), False)]
         assert np.all(r0[:, 3:6] == H)
+
+
+class _Instance:
+    """One instance of a batch seen through the single-lattice interface the
+    lock-step comparison uses (stepping advances the whole batch)."""
+
+    def __init__(self, batch, i):
+        self.b, self.i = batch, i
+
+    def step(self, n):
+        self.b.step(n)
+
+    def events(self):
+        return self.b.events(self.i)
+
+    def fields(self, names=None):
+        return self.b.fields(self.i) if names is None else self.b.fields(self.i, names)
+
+    def observe(self):
+        return self.b.observe(self.i)
+
+
+@pytest.mark.timeout(900)
+def test_paper_scale_capillary_against_oracle(oracle_mod):
+    """One paper-scale capillary (L = 500, H = 25, k_r = 8e-4; Figs. 2-3) through
+    the batched HIP path, beside the L = 1000 one in the same batch, and
+    through the FP64 oracle for 20,000 steps, compared every 2000 steps: the
+    front within 0.01 lu, Delta e and the closure step exactly, the growth
+    events exactly up to certified ties (a node whose precipitate crosses the
+    threshold within the two precisions' difference; reported, at most 3),
+    and at the end every field within the parity tolerances."""
+    from paper_1309_6726_amd import lbm
+    probs = [_problem(500, 25, 8e-4, 0), _problem(1000, 25, 8e-4, 1)]
+    PT.say("[paper scale vs oracle] L 500, H 25, k_r 8e-4: 20000 steps, batched with L 1000")
+    b = lbm.Batch(probs, graph_chunk=500)
+    orc = oracle_mod.Oracle.from_problem(probs[0])
+    inst = _Instance(b, 0)
+
+    def check(t, sim, orc):
+        go, oo = sim.observe(), orc.observe()
+        assert abs(go["front_z"] - oo["front_z"]) <= PT.Z_TOL, (t, go["front_z"], oo["front_z"])
+        assert go["delta_e"] == oo["delta_e"], (t, go["delta_e"], oo["delta_e"])
+        assert go["closure_step"] == oo["closure_step"], (t, go["closure_step"], oo["closure_step"])
+        PT.say(f"  step {t}: z {go['front_z']:.4f} (oracle {oo['front_z']:.4f}), "
+               f"delta_e {go['delta_e']}")
+
+    nev, ties, dm, orc = PT.run_windows(inst, orc, 20_000, 2000, threshold=1.0, allow_ties=True,
+                                        field_check=check)
+    d = PT.compare_fields(b.fields(0), orc.fields(), where="paper scale step 20000")
+    PT.say(f"  20000 steps: {nev} events, {ties} certified ties, max |dm| {dm:.2e}; fields {d}")
+    assert nev > 100 and ties <= 3 and orc.observe()["front_z"] > 10.0
+    b.close()

@@ -1,10 +1,7 @@
-"""GPU (HIP, FP32) vs FP64 oracle parity through the C ABI.
+"""GPU (HIP: FP32 state, FP64 arithmetic) vs FP64 oracle parity through the C ABI.
 
 Every test prints the case it runs before touching the GPU.
 """
-
-import math
-import os
 
 import numpy as np
 import pytest
@@ -153,34 +150,36 @@ def test_d2q4_checkpoint_rejects_rest_population(lbm):
     assert e.value.status == lbm.LBM_EINVAL
 
 
-def test_config1_events_exact_windows(lbm, oracle_mod):
-    """1024x64 reactive capillary (W=48, D=0.05, k_r=1e-3, threshold 1):
-    growth events compared exactly in windows of 500 steps, fields within
-    tolerance at every window boundary.  The full 50k-step comparison runs
-    with LBM_FULL_PARITY=1."""
+@pytest.mark.timeout(900)
+def test_config1_events_exact_50k_steps(lbm, oracle_mod):
+    """1024x64 reactive capillary (W=48, D=0.05, k_r=1e-3, threshold 1) over
+    its full 50,000 steps: growth events compared exactly in windows of 1000
+    steps (no difference tolerated), fields within tolerance, the front, Delta
+    e, the closure step and both ledgers at every window boundary."""
     prob = inputs.config1(seed=0)
-    nsteps = 50_000 if os.environ.get("LBM_FULL_PARITY") else 3000
-    PT.say(f"[cfg1] {prob.name}: {nsteps} steps in windows of 500")
+    nsteps = 50_000
+    PT.say(f"[cfg1] {prob.name}: {nsteps} steps in windows of 1000")
     sim = lbm.Sim.from_problem(prob)
     orc = oracle_mod.Oracle.from_problem(prob)
     o0 = orc.observe()
+    MASS_REL = 1e-6
 
     def check(step, sim, orc):
         go, oo = sim.observe(), orc.observe()
         assert abs(go["front_z"] - oo["front_z"]) <= PT.Z_TOL, (step, go["front_z"], oo["front_z"])
         assert go["delta_e"] == oo["delta_e"] and go["closure_step"] == oo["closure_step"]
+        assert go["n_solid"] == oo["n_solid"]
         tot = go["solute"] + go["precipitate"] + go["solute_removed"]
         assert abs(tot - o0["solute"]) <= MASS_REL * o0["solute"]
         for s in range(2):
             assert abs(go["mass"][s] + go["mass_removed"][s] - o0["mass"][s]) <= MASS_REL * o0["mass"][s]
-        if step % 1000 == 0:
-            _fields_cmp(sim, orc, f"cfg1 step {step}")
+        _fields_cmp(sim, orc, f"cfg1 step {step}")
 
-    MASS_REL = 1e-6
-    nev, ties, dm, orc = PT.run_windows(sim, orc, nsteps, 500, prob.params.threshold,
-                                        field_check=check)
-    PT.say(f"  cfg1: {nev} events, {ties} certified ties, max |dm| {dm:.2e}")
-    assert nev > 0
+    nev, _, dm, orc = PT.run_windows(sim, orc, nsteps, 1000, field_check=check)
+    oo = orc.observe()
+    PT.say(f"  cfg1: {nev} growth events identical over {nsteps} steps, max |dm| {dm:.2e}, "
+           f"delta_e {oo['delta_e']}, closure step {oo['closure_step']}")
+    assert nev > 1000
 
 
 @pytest.mark.parametrize("scheme", ["moments", "populations"])
@@ -303,44 +302,36 @@ def test_checkpoint_resume_bitwise(lbm):
     assert a.observe() == b.observe()
 
 
-def test_config2_full_size_sampled_patches(lbm, oracle_mod):
-    """2048x2048 porous preform at full size in the launch configuration the
-    benchmark's autotuner picks for it on MI355X (moment step, 64x12 tiles,
-    non-temporal load hint).  After n steps a node depends only on the
-    initial state within Chebyshev distance 2n (streaming 1 + force stencil 1
-    per step), so the oracle can compute sampled 48x48 patches exactly from
-    (48+4n)^2 windows."""
+@pytest.mark.timeout(900)
+def test_config2_full_domain_1000_steps_and_first_events(lbm, oracle_mod):
+    """2048x2048 porous preform, whole lattice, in the launch configuration
+    the benchmark's autotuner picks for it on MI355X (moment step, 64x12
+    tiles, non-temporal load hint), against the oracle on all host threads:
+    every field at step 1000 (densities 1e-5, velocity 1e-6, concentration
+    1e-5, precipitate 1e-6), masses and ledgers, and the growth events of the
+    preform compared exactly through step 1300 (the first ones appear near
+    step 770)."""
     prob = inputs.config2(seed=0)
-    n = 40
-    PT.say(f"[cfg2] {prob.name}: {n} steps, sampled patches")
+    PT.say(f"[cfg2] {prob.name}: full domain, 1000 + 300 steps")
     sim = lbm.Sim.from_problem(prob, tile=(64, 12))
     sim.set_load_hint(1)
-    o0 = sim.observe()
-    sim.step(n)
-    gf = sim.fields()
-    go = sim.observe()
-    for s in range(2):
-        assert abs(go["mass"][s] - o0["mass"][s]) <= 1e-6 * o0["mass"][s]
-    tot0 = o0["solute"]
-    tot = go["solute"] + go["precipitate"] + go["solute_removed"]
-    assert abs(tot - tot0) <= 1e-6 * tot0
-    ny, nx = prob.solid.shape
-    rng = np.random.default_rng(0)
-    ps, R = 48, 2 * n
-    centers = [(30, 24), (1000, 1000), (2040, 2047)] + \
-        [(int(x), int(y)) for x, y in zip(rng.integers(0, nx, 4), rng.integers(0, ny, 4))]
-    for (cx, cy) in centers:
-        xs = np.arange(cx - ps // 2 - R, cx + ps // 2 + R) % nx
-        ys = np.arange(cy - ps // 2 - R, cy + ps // 2 + R) % ny
-        sub = np.ix_(ys, xs)
-        p = prob.params.replace(nx=len(xs), ny=len(ys))
-        orc = oracle_mod.Oracle(p, prob.solid[sub], prob.rho1[sub], prob.rho2[sub], prob.conc[sub])
-        orc.step(n)
-        of = orc.fields()
-        inner = (slice(R, R + ps), slice(R, R + ps))
-        gsub = {k: gf[k][sub][inner] for k in gf}
-        osub = {k: of[k][inner] for k in of}
-        PT.compare_fields(gsub, osub, where=f"cfg2 patch at {cx},{cy}", m_tol=1e-7)
+    orc = oracle_mod.Oracle.from_problem(prob)
+    o0 = orc.observe()
+    for n in (1000, 1300):
+        sim.step(n - orc.steps)
+        orc.step(n - orc.steps)
+        go, oo = sim.observe(), orc.observe()
+        d = _fields_cmp(sim, orc, f"cfg2 step {n}", m_tol=1e-6)
+        for s in range(2):
+            assert abs(go["mass"][s] + go["mass_removed"][s] - o0["mass"][s]) <= 1e-6 * o0["mass"][s]
+            assert abs(go["mass"][s] - oo["mass"][s]) <= 1e-6 * oo["mass"][s]
+        tot = go["solute"] + go["precipitate"] + go["solute_removed"]
+        assert abs(tot - o0["solute"]) <= 1e-6 * o0["solute"]
+        ge, oe = PT.event_set(sim.events()), PT.event_set(orc.events())
+        assert ge == oe, (n, len(ge - oe), len(oe - ge))
+        assert go["n_solid"] == oo["n_solid"]
+        PT.say(f"  step {n}: {len(ge)} growth events identical; {d}")
+    assert len(ge) >= 50
 
 
 def test_edge_lattices(lbm, oracle_mod):
