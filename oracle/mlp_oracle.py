@@ -68,6 +68,36 @@ def loss_and_grad(p, x, t, lo, hi, w=None):
     return loss, g
 
 
+def grad_error_scale(p, x, t, lo, hi, w=None):
+    """Element-wise magnitude scale of the packed gradient: the gradient
+    computation of loss_and_grad with every quantity replaced by a bound on its
+    magnitude.  The forward pass uses |W| and |b| and no ReLU cut
+    (|relu(z)| <= |z| <= |W| |a| + |b|); the output gradient uses
+    2 w (|y| + |t|) / (rows sum w) >= |dL/dy|; deltas pass back through |W|
+    and every unit.  An entry is thus at least the sum of the magnitudes of
+    all products that make up that gradient entry (and of those that would,
+    were a ReLU decided the other way), so a computation whose every product
+    carries a relative error of at most u errs on it by at most
+    (products in the chain) * u times this scale, to first order."""
+    a = np.abs(normalise(x, lo, hi))
+    acts = [a]
+    layers = [(np.abs(W), np.abs(b)) for W, b in unpack(np.asarray(p, dtype=np.float64))]
+    for W, b in layers:
+        a = a @ W.T + b
+        acts.append(a)
+    rows = a.shape[0]
+    w = np.ones(SIZES[-1]) if w is None else np.asarray(w, dtype=np.float64)
+    scale = 1.0 / (rows * w.sum())
+    d = 2.0 * w * (a + np.abs(t)) * scale
+    grads = [None] * len(layers)
+    for k in range(len(layers) - 1, -1, -1):
+        W, _ = layers[k]
+        grads[k] = (d.T @ acts[k], d.sum(axis=0))
+        if k > 0:
+            d = d @ W
+    return np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in grads])
+
+
 def adam_step(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g

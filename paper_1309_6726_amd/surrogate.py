@@ -198,15 +198,6 @@ def generate(seed: int, n: int, T: int, *, chunk: int = 512, device="cuda:0", lo
     return rows, inputs.surrogate_inputs(rows), fronts, closure, time.perf_counter() - t0
 
 
-def row_weights(x, fronts, T, cap=400.0):
-    """Per-run loss weights (S / max(z(T), 1))^2, capped and normalised to
-    mean 1: with targets z / S the weighted loss then follows the front error
-    relative to the travel, also for fronts that stall or recede."""
-    S = washburn_scale(x, T)
-    w = np.minimum((S / np.maximum(fronts[:, -1], 1.0)) ** 2, cap)
-    return w / w.mean()
-
-
 def train(net: Surrogate, x, y, *, epochs=3000, batch=256, lr=2e-3, lr_min=2e-5, seed=0,
           log=None, log_every=500, weights=None):
     """Adam with a cosine learning-rate schedule; permutations from the seeded
@@ -227,69 +218,43 @@ def train(net: Surrogate, x, y, *, epochs=3000, batch=256, lr=2e-3, lr_min=2e-5,
     return hist
 
 
-def predict_runs(net: Surrogate, rows, T: int, *, device="cuda:0"):
-    """Fronts and closure steps for sweep rows: the network inside its
-    training box, the batched lattice Boltzmann model outside it.
-    Returns (fronts, closure, in_box mask, lb_seconds)."""
-    x = inputs.surrogate_inputs(rows)
-    ok = in_box(x, net.lo, net.hi)
-    fronts = np.zeros((len(rows), NSLOTS))
-    closure = np.zeros(len(rows), dtype=np.int64)
-    if ok.any():
-        y = net.predict(x[ok])
-        f, c = decode(x[ok], y.astype(np.float64), T)
-        fronts[ok], closure[ok] = f, c
-    lb_sec = 0.0
-    if (~ok).any():
-        idx = np.nonzero(~ok)[0]
-        probs = [inputs.sweep_problem(rows[i], int(i), steps=T) for i in idx]
-        f, c, lb_sec, _ = sweep.run_batched(probs, T, NSLOTS, device=device)
-        fronts[idx], closure[idx] = f, c
-    return fronts, closure, ok, lb_sec
+def joint_gates(travel, spread, err, target=0.01, p95=0.02, min_frac=0.25):
+    """The (travel gate, spread gate) pair that answers the most runs among
+    those whose answered runs (predicted travel >= travel gate and relative
+    spread <= spread gate) have mean front error <= target and a 95th
+    percentile of the error <= p95, and make up at least min_frac of the runs.
+    Travel gates are whole lattice units 0..100.  Returns (inf, -1.0) when no
+    pair qualifies (every query then goes to the lattice Boltzmann model)."""
+    travel, spread, err = (np.asarray(v, dtype=np.float64) for v in (travel, spread, err))
+    n = len(err)
+    need = int(math.ceil(min_frac * n))
+    best, best_n = (float("inf"), -1.0), 0
+    for z in np.arange(0.0, 101.0, 1.0):
+        sel = np.nonzero(travel >= z)[0]
+        if len(sel) < max(need, 1):
+            break
+        order = sel[np.argsort(spread[sel], kind="stable")]
+        e = err[order]
+        sp = spread[order]
+        cmean = np.cumsum(e) / np.arange(1, len(e) + 1)
+        for k in range(len(e), 0, -1):  # largest answered set first
+            if k < need or k <= best_n:
+                break
+            if k < len(e) and sp[k] == sp[k - 1]:
+                continue  # a gate at sp[k-1] would also admit run k
+            if cmean[k - 1] <= target and np.quantile(e[:k], 0.95) <= p95:
+                best, best_n = (float(z), float(sp[k - 1])), k
+                break
+    return best
 
 
-def choose_spread_gate(spread, err, target=0.005, min_frac=0.25) -> float:
-    """Largest relative spread such that the runs at or below it have mean
-    front error <= target and make up at least min_frac of the runs
-    (-1: none qualifies, every query goes to the lattice Boltzmann model)."""
-    order = np.argsort(spread, kind="stable")
-    n = np.arange(1, len(order) + 1)
-    cum = np.cumsum(np.asarray(err, dtype=np.float64)[order]) / n
-    ok = np.nonzero((cum <= target) & (n >= min_frac * len(order)))[0]
-    return float(np.asarray(spread)[order][ok[-1]]) if len(ok) else -1.0
-
-
-def choose_gates(model, x, fronts, T, target=0.005, min_frac=0.25):
-    """Both gates of an ensemble from held-back runs: the predicted-travel
-    gate (choose_gate) and the spread gate, each for mean error <= target."""
+def choose_gates(model, x, fronts, T, target=0.01, p95=0.02, min_frac=0.25):
+    """Both gates of an ensemble from held-back runs whose lattice Boltzmann
+    fronts are known (joint_gates on its predictions)."""
     y, spread = model.predict_with_spread(x, T)
     f, _ = decode(x, y, T)
     err = front_error(f, fronts)
-
-    class _Fixed:
-        def predict(self, _x):
-            return y
-    return (choose_gate(_Fixed(), x, fronts, T, target, min_frac),
-            choose_spread_gate(spread, err, target, min_frac))
-
-
-def choose_gate(net: Surrogate, x, fronts, T, target=0.01, min_frac=0.25):
-    """Smallest predicted travel z_hat(T) (lattice units) such that the runs
-    predicted at or above it have mean front error <= target, chosen on runs
-    the network has not been trained on.  Runs predicted below it (fronts that
-    hardly enter, stall or recede under strong surface growth, where the error
-    relative to their small travel is large) go to the lattice Boltzmann model."""
-    y = net.predict(x).astype(np.float64)
-    f, _ = decode(x, y, T)
-    err = front_error(f, fronts)
-    travel = f[:, -1]
-    for z in np.arange(0.0, 101.0, 1.0):
-        sel = travel >= z
-        if sel.sum() < min_frac * len(x):
-            break
-        if err[sel].mean() <= target:
-            return float(z)
-    return float("inf")
+    return joint_gates(f[:, -1], spread, err, target, p95, min_frac)
 
 
 def answer(net, rows, T: int, gate, *, device="cuda:0"):
@@ -297,7 +262,8 @@ def answer(net, rows, T: int, gate, *, device="cuda:0"):
     it is in its box and confident, by the batched lattice Boltzmann model
     otherwise.  gate: minimum predicted travel z_hat(T) in lattice units, or
     for an ensemble (travel gate, spread gate).  Returns (fronts, closure,
-    used_net mask, net_seconds, lb_seconds)."""
+    used_net mask, net_seconds, lb_seconds); lb_seconds covers building the
+    fallback batch as well as running it."""
     x = inputs.surrogate_inputs(rows)
     ok = in_box(x, net.lo, net.hi)
     fronts = np.zeros((len(rows), NSLOTS))

@@ -45,17 +45,35 @@ def test_forward_matches_fp64_oracle(surr):
     assert np.array_equal(back, p)
 
 
-def test_gradients_match_fp64_oracle(surr):
-    PT.say("[surrogate gradients] 200 rows")
+# Element-wise bound on the BF16-MFMA gradients.  Every product in the chain
+# that forms a weight gradient has both operands rounded to BF16 (8-bit
+# significand, relative error <= 2^-9 each, so <= 2^-8 per product) and is
+# accumulated in FP32 (<= 256 terms x 2^-24, negligible).  The gradient of a
+# layer passes through at most 4 forward products, the BF16 rounding of dL/dy
+# (2^-9), 3 backward products and the weight-gradient product: to first order
+# at most 8.5 units of 2^-8 relative to the sum of the magnitudes of its
+# products, which the oracle's grad_error_scale bounds entry by entry.
+GRAD_BOUND = 9.0 * 2.0 ** -8
+
+
+@pytest.mark.parametrize("seed", [8, 11])
+def test_gradients_match_fp64_oracle(surr, seed):
+    PT.say(f"[surrogate gradients] 200 rows, weights seed {seed}")
     net = surr.Surrogate(max_batch=256, max_data=16)
-    p = inputs.mlp_init_params(8).astype(np.float32)
+    p = inputs.mlp_init_params(seed).astype(np.float32)
     net.set_params(p)
     w = np.linspace(0.5, 2.0, 65).astype(np.float32)
     net.set_loss_weights(w)
-    x, t = _data(200, 2)
+    x, t = _data(200, seed - 6)
     loss, g = net.gradients(x, t)
-    lo_, go = M.loss_and_grad(p.astype(np.float64), x, t, net.lo, net.hi, w.astype(np.float64))
+    p64, w64 = p.astype(np.float64), w.astype(np.float64)
+    lo_, go = M.loss_and_grad(p64, x, t, net.lo, net.hi, w64)
+    E = M.grad_error_scale(p64, x, t, net.lo, net.hi, w64)
     assert abs(loss - lo_) <= 1e-2 * lo_
+    err = np.abs(g.astype(np.float64) - go)
+    # every entry within the first-order bound of its own magnitude scale
+    worst = float((err / np.maximum(E, 1e-300)).max())
+    assert (err <= GRAD_BOUND * E).all(), worst
     off = 0
     for fi, fo in zip(inputs.MLP_SIZES[:-1], inputs.MLP_SIZES[1:]):
         for size in (fi * fo, fo):
@@ -63,6 +81,7 @@ def test_gradients_match_fp64_oracle(surr):
             assert _rel(a, b) <= 2e-2, (fi, fo, size, _rel(a, b))
             assert float(a @ b) / (np.linalg.norm(a) * np.linalg.norm(b)) > 0.999
             off += size
+    PT.say(f"  largest error / magnitude scale {worst:.2e} (bound {GRAD_BOUND:.2e})")
 
 
 def test_adam_kernel_mirrors_oracle_adam(surr):

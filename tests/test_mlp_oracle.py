@@ -1,5 +1,7 @@
 """Pins of the FP64 surrogate MLP oracle: finite-difference gradients, the
-closed-form first Adam step, and a hand-wired network with a known output."""
+closed-form first Adam step, a hand-wired network with a known output, and
+the gradient's magnitude scale (an upper bound of every entry, equal to the
+gradient when no sign can cancel)."""
 
 import numpy as np
 
@@ -67,3 +69,28 @@ def test_hand_wired_network_reproduces_normalised_inputs():
     # the packed layout is the documented one: W1 first, then b1, ...
     assert layers[0][0].shape == (256, 5) and layers[3][0].shape == (65, 256)
     assert inputs.MLP_NPARAMS == 149825
+
+
+def test_grad_error_scale_bounds_and_equality_case():
+    """The scale bounds every gradient entry in magnitude; when every weight,
+    bias and normalised input is positive and the targets are zero, no product
+    changes sign, no ReLU cuts, and dL/dy = 2 w y / (rows sum w) = 2 w (|y| +
+    |t|) / (rows sum w), so the scale equals the gradient itself."""
+    x, t, lo, hi = _data(9, 3)
+    w = np.linspace(0.5, 2.0, 65)
+    for seed in (4, 5):
+        p = inputs.mlp_init_params(seed)
+        _, g = M.loss_and_grad(p, x, t, lo, hi, w)
+        E = M.grad_error_scale(p, x, t, lo, hi, w)
+        assert (E >= np.abs(g) * (1 - 1e-12)).all()
+        assert (E > 0).mean() > 0.99
+    rng = np.random.default_rng(6)
+    p = np.abs(inputs.mlp_init_params(7)) + 1e-3
+    xp = hi - (hi - lo) * rng.uniform(0.05, 0.45, size=(9, 5))  # normalised inputs in (0, 1)
+    xp[:, 2] = 10 ** (np.log10(hi[2]) - rng.uniform(0.05, 0.45, 9) * (np.log10(hi[2]) - np.log10(lo[2])))
+    assert (M.normalise(xp, lo, hi) > 0).all()
+    t0 = np.zeros((9, 65))
+    _, g = M.loss_and_grad(p, xp, t0, lo, hi, w)
+    E = M.grad_error_scale(p, xp, t0, lo, hi, w)
+    assert (g > 0).all()
+    assert np.allclose(E, g, rtol=1e-12, atol=0)

@@ -1,5 +1,5 @@
 """Host-side pieces of the surrogate pipeline (no GPU): the error metric,
-target encoding/decoding, the confidence gate and the out-of-range queries."""
+target encoding/decoding, the confidence gates and the out-of-range queries."""
 
 import numpy as np
 
@@ -33,37 +33,33 @@ def test_targets_roundtrip_and_washburn_scale():
     assert v[1] > v[0] > v[2]
 
 
-def test_gate_picks_smallest_travel_meeting_target():
-    class Fixed:
-        def __init__(self, y):
-            self.y = y
-
-        def predict(self, x):
-            return self.y
-    T = 10000
-    x = np.tile([[30.0, 800.0, 1e-3, 30.0, 1.0]], (40, 1))
-    Sx = S.washburn_scale(x, T)[0]
-    true = np.tile(np.linspace(0, 1, 64), (40, 1)) * np.linspace(0.5, 40, 40)[:, None]
-    pred = true.copy()
-    pred[:10] += 0.5                     # small-travel runs carry an absolute error
-    y = np.concatenate([pred / Sx, np.ones((40, 1))], axis=1)
-    g = S.choose_gate(Fixed(y), x, true, T, target=0.01)
-    sel = true[:, -1] >= g
-    assert sel.sum() >= 10 and S.front_error(pred, true)[sel].mean() <= 0.01
-    assert g > true[9, -1] * 0.5
-
-
-def test_spread_gate_keeps_the_agreeing_runs():
-    """Runs sorted by ensemble spread: the gate is the largest spread whose
-    runs at or below it average <= target error, with a minimum coverage."""
-    spread = np.array([0.01, 0.02, 0.03, 0.04, 0.5, 0.6, 0.7, 0.8])
-    err = np.array([0.001, 0.002, 0.003, 0.004, 0.05, 0.06, 0.07, 0.08])
-    g = S.choose_spread_gate(spread, err, target=0.005, min_frac=0.25)
-    assert g == 0.04
-    assert S.choose_spread_gate(spread, err, target=0.0005, min_frac=0.25) == -1.0
-    # the mean error over the selected runs is what counts, not each run's
-    err2 = np.array([0.009, 0.001, 0.001, 0.001, 0.05, 0.06, 0.07, 0.08])
-    assert S.choose_spread_gate(spread, err2, target=0.005, min_frac=0.25) == 0.04
+def test_joint_gates_bound_mean_and_95th_percentile():
+    """Twenty runs: errors grow with the spread, and the five runs of smallest
+    travel carry a large error whatever their spread.  Worked by hand: with
+    travel gate 6 lu the runs left are 5..19 (spread 0.05..0.19, error
+    0.001..0.015 except run 17 at 0.05); the largest prefix by spread whose
+    mean is <= 1% and whose 95th percentile is <= 2% is runs 5..16 (mean
+    0.0065, 95th percentile 0.0114), so the gates are (6, 0.16)."""
+    n = 20
+    travel = np.arange(n, dtype=float) + 1.0          # 1..20 lu
+    spread = np.arange(n, dtype=float) / 100.0        # 0.00..0.19
+    err = np.full(n, 0.3)                              # small travel: large error
+    err[5:] = (np.arange(5, n) - 4) / 1000.0           # 0.001..0.015
+    err[17] = 0.05                                     # one outlier among the agreeing runs
+    g_t, g_s = S.joint_gates(travel, spread, err, target=0.01, p95=0.02, min_frac=0.25)
+    assert (g_t, g_s) == (6.0, 0.16)
+    sel = (travel >= g_t) & (spread <= g_s)
+    assert sel.sum() == 12 and err[sel].mean() <= 0.01 and np.quantile(err[sel], 0.95) <= 0.02
+    # with the mean bound relaxed, the 95th percentile alone keeps the outlier out
+    g_t2, g_s2 = S.joint_gates(travel, spread, err, target=1.0, p95=0.02, min_frac=0.25)
+    sel2 = (travel >= g_t2) & (spread <= g_s2)
+    assert (g_t2, g_s2) == (6.0, 0.16) and np.quantile(err[sel2], 0.95) <= 0.02
+    # nothing qualifies: every query goes to the lattice Boltzmann model
+    assert S.joint_gates(travel, spread, err, target=1e-4) == (float("inf"), -1.0)
+    # equal spreads are admitted together or not at all
+    sp = np.zeros(n)
+    g = S.joint_gates(travel, sp, err, target=0.01, p95=0.02, min_frac=0.25)
+    assert g == (float("inf"), -1.0) or ((travel >= g[0]) & (sp <= g[1])).sum() == (travel >= g[0]).sum()
 
 
 def test_out_of_range_rows_are_outside_the_box():
