@@ -323,6 +323,18 @@ lbm_status surr_gradients(surr_net* s, const float* x, const float* y, int32_t n
                           double* loss);
 /* y [n x 65] for x [n x 5] (host arrays). */
 lbm_status surr_predict(surr_net* s, const float* x, int32_t n, float* y);
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same prediction as surr_predict, with x [n x 5] and y [n x 65] FP32 arrays
+ * in device memory, queued on `stream` (whose device must be current) without
+ * waiting for it.  The activations live in a static array of the library
+ * (3.2 MB per GPU, held until the process ends), so n is 1..1024 per call
+ * (more is LBM_EINVAL) and no memory is allocated.  Every call on one GPU
+ * uses the same array: calls that overlap on a GPU (concurrent streams or
+ * threads) race and must be ordered by the caller.  The handle is only read;
+ * it must not be trained concurrently. */
+lbm_status surr_predict_noalloc(const surr_net* s, const float* x, int32_t n, float* y,
+                                void* stream);
 void surr_destroy(surr_net* s);
 
 void lbm_destroy(lbm_sim* sim);

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -75,6 +76,44 @@ SLayout slayout(int max_batch, int max_data) {
   S.loss = take(8);
   S.total = off;
   return S;
+}
+
+// ---- scratch of the prediction that allocates nothing ---------------------
+// surr_predict_noalloc keeps its activations in this file-scope device array
+// instead of the handle's workspace; every GPU the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not a device address: host code uses the address that
+// scratch_ptr() looked up for the device.
+constexpr int SCRATCH_ROWS = 1024;  // most query rows per call
+constexpr size_t SC_X0 = 0;                                             // BF16 [R x KIN]
+constexpr size_t SC_X0T = SC_X0 + (size_t)SCRATCH_ROWS * KIN * 2;        // BF16 [KIN x R]
+constexpr size_t SC_HA = SC_X0T + (size_t)KIN * SCRATCH_ROWS * 2;        // BF16 [R x NHID]
+constexpr size_t SC_HB = SC_HA + (size_t)SCRATCH_ROWS * NHID * 2;        // BF16 [R x NHID]
+constexpr size_t SC_HF = SC_HB + (size_t)SCRATCH_ROWS * NHID * 2;        // FP32 [R x NHID] (unread)
+constexpr size_t SC_HT = SC_HF + (size_t)SCRATCH_ROWS * NHID * 4;        // BF16 [NHID x R] (unread)
+constexpr size_t SC_Y = SC_HT + (size_t)NHID * SCRATCH_ROWS * 2;         // FP32 [R x NOUTP]
+constexpr size_t SCRATCH_BYTES = SC_Y + (size_t)SCRATCH_ROWS * NOUTP * 4;  // 3.2 MB
+
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev, which must be the current
+// device; looked up once per device and kept.
+lbm_status scratch_ptr(int dev, char** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch[dev] = (char*)p;
+  }
+  *out = g_scratch[dev];
+  return LBM_OK;
 }
 
 }  // namespace
@@ -221,6 +260,11 @@ lbm_status surr_init(const double* lo, const double* hi, int32_t max_batch, int3
   if (e == hipSuccess) e = hipMemcpyAsync(s->ws + s->S.lw, lw, sizeof lw, hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) { delete s; return fail(LBM_EDEVICE, "surrogate init: %s", hipGetErrorString(e)); }
+  // the scratch of surr_predict_noalloc on this (the current) device
+  int dev = 0;
+  char* sc = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess) { delete s; return fail(LBM_EDEVICE, "no current device"); }
+  if ((st = scratch_ptr(dev, &sc)) != LBM_OK) { delete s; return st; }
   *out = s;
   return LBM_OK;
 }
@@ -355,6 +399,48 @@ lbm_status surr_predict(surr_net* s, const float* x, int32_t n, float* y) {
                         hipMemcpyDeviceToHost, s->stream));
   }
   HC(hipStreamSynchronize(s->stream));
+  return LBM_OK;
+}
+
+lbm_status surr_predict_noalloc(const surr_net* s, const float* x, int32_t n, float* y,
+                                void* stream) {
+  if (!s || !x || !y) return fail(LBM_EINVAL, "NULL argument");
+  if (n < 1 || n > SCRATCH_ROWS)
+    return fail(LBM_EINVAL, "surr_predict_noalloc takes 1..%d rows per call, got %d", SCRATCH_ROWS, n);
+  const hipStream_t st = (hipStream_t)stream;
+  int cur = 0, dev = 0;
+  HC(hipGetDevice(&cur));
+  dev = cur;
+  if (st) HC(hipStreamGetDevice(st, &dev));
+  if (dev != cur) return fail(LBM_EINVAL, "the stream's device %d is not the current device %d", dev, cur);
+  char* sc = nullptr;
+  lbm_status r = scratch_ptr(dev, &sc);
+  if (r != LBM_OK) return r;
+  const SLayout& S = s->S;
+  const int B = (n + 31) / 32 * 32;
+  HC(gather(x, nullptr, nullptr, nullptr, n, B, s->at<float>(S.lo), s->at<float>(S.hi),
+            (__bf16*)(sc + SC_X0), (__bf16*)(sc + SC_X0T), nullptr, nullptr, st));
+  const __bf16* in = (const __bf16*)(sc + SC_X0);
+  int ldin = KIN;
+  for (int l = 0; l < 3; ++l) {
+    __bf16* out = (__bf16*)(sc + (l % 2 == 0 ? SC_HA : SC_HB));
+    GemmArgs g{};
+    g.A = in; g.lda = ldin; g.Bt = s->at<__bf16>(S.wb[l]); g.ldb = LK[l];
+    g.M = B; g.N = LN[l]; g.K = LK[l];
+    g.bias = s->at<float>(S.p[l]) + (size_t)LN[l] * LK[l];
+    g.outf = (float*)(sc + SC_HF); g.outb = out; g.outt = (__bf16*)(sc + SC_HT);
+    g.ldo = NHID; g.ldt = B;
+    HC(gemm(EPI_HIDDEN, g, st));
+    in = out;
+    ldin = NHID;
+  }
+  GemmArgs g{};
+  g.A = in; g.lda = NHID; g.Bt = s->at<__bf16>(S.wb[3]); g.ldb = NHID;
+  g.M = B; g.N = NOUTP; g.K = NHID;
+  g.bias = s->at<float>(S.p[3]) + (size_t)NOUTP * NHID;
+  g.outf = (float*)(sc + SC_Y); g.ldo = NOUTP;
+  HC(gemm(EPI_OUTPUT, g, st));
+  HC(hipMemcpy2DAsync(y, NOUT * 4, sc + SC_Y, NOUTP * 4, NOUT * 4, n, hipMemcpyDeviceToDevice, st));
   return LBM_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTS = ("lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_observe", "lbm_fi
            "lbm_batch_fields", "lbm_batch_events", "lbm_batch_autotune", "lbm_batch_destroy",
            "surr_workspace_bytes", "surr_init", "surr_set_params", "surr_get_params",
            "surr_set_loss_weights", "surr_set_data", "surr_train_epoch", "surr_gradients",
-           "surr_predict", "surr_destroy")
+           "surr_predict", "surr_predict_noalloc", "surr_destroy")
 
 
 class LbmError(RuntimeError):
@@ -135,6 +135,7 @@ def lib():
             "surr_train_epoch": [P, P, C.c_int32, C.c_float, C.POINTER(C.c_double)],
             "surr_gradients": [P, P, P, C.c_int32, P, C.POINTER(C.c_double)],
             "surr_predict": [P, P, C.c_int32, P],
+            "surr_predict_noalloc": [P, P, C.c_int32, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)

@@ -147,6 +147,20 @@ class Surrogate:
         lbm.check(lbm.lib().surr_predict(self.h, x.ctypes.data, x.shape[0], y.ctypes.data))
         return y
 
+    def predict_noalloc(self, x_dev, y_dev, stream=None):
+        """surr_predict_noalloc: x_dev [n x 5] and y_dev [n x 65] are contiguous
+        FP32 torch tensors on the handle's GPU; queued on `stream` (default:
+        the handle's), nothing allocated, no synchronisation."""
+        import torch
+        assert x_dev.dtype == torch.float32 and y_dev.dtype == torch.float32
+        assert x_dev.is_contiguous() and y_dev.is_contiguous()
+        n = x_dev.shape[0]
+        assert x_dev.shape == (n, inputs.MLP_SIZES[0]) and y_dev.shape == (n, inputs.MLP_SIZES[-1])
+        st = self.stream if stream is None else stream
+        lbm.check(lbm.lib().surr_predict_noalloc(self.h, C.c_void_p(x_dev.data_ptr()), n,
+                                                 C.c_void_p(y_dev.data_ptr()),
+                                                 C.c_void_p(st.cuda_stream)))
+
 
 class Ensemble:
     """K networks trained from different seeds (initial weights and minibatch
