@@ -65,18 +65,21 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const GemmArgs g) {
 // resident data set: normalised inputs (BF16, row-major and transposed) and
 // FP32 targets; padding rows and columns are zero.  Inputs x = (W, L, k_r,
 // theta, threshold); x' = 2 (x - lo) / (hi - lo) - 1, with log10 applied to
-// k_r and its bounds.
+// k_r and its bounds.  One thread per (row, column) of the KIN input columns
+// followed by the NOUTP target columns, rows fastest (so the transposed input
+// stores are coalesced); the row weight is written by column 0.
 __global__ void k_gather(const float* __restrict__ X, const float* __restrict__ Y,
                          const float* __restrict__ RW, const int32_t* __restrict__ idx, int rows,
                          int Bp, const float* __restrict__ lo, const float* __restrict__ hi,
                          __bf16* __restrict__ x0, __bf16* __restrict__ x0t, float* __restrict__ t,
                          float* __restrict__ rw) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= Bp) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ncol = KIN + (t ? NOUTP : 0);
+  if (e >= Bp * ncol) return;
+  const int r = e % Bp, j = e / Bp;
   const bool real = r < rows;
   const int src = real ? (idx ? idx[r] : r) : 0;
-  if (rw) rw[r] = real ? (RW ? RW[src] : 1.0f) : 0.0f;
-  for (int j = 0; j < KIN; ++j) {
+  if (j < KIN) {
     float v = 0.0f;
     if (real && j < NIN) {
       float x = X[(size_t)src * NIN + j], a = lo[j], b = hi[j];
@@ -85,10 +88,10 @@ __global__ void k_gather(const float* __restrict__ X, const float* __restrict__ 
     }
     x0[(size_t)r * KIN + j] = (__bf16)v;
     x0t[(size_t)j * Bp + r] = (__bf16)v;
-  }
-  if (t) {
-    for (int j = 0; j < NOUTP; ++j)
-      t[(size_t)r * NOUTP + j] = (real && Y && j < NOUT) ? Y[(size_t)src * NOUT + j] : 0.0f;
+    if (j == 0 && rw) rw[r] = real ? (RW ? RW[src] : 1.0f) : 0.0f;
+  } else {
+    const int c = j - KIN;
+    t[(size_t)r * NOUTP + c] = (real && Y && c < NOUT) ? Y[(size_t)src * NOUT + c] : 0.0f;
   }
 }
 
@@ -188,7 +191,8 @@ hipError_t gemm(int epi, const GemmArgs& g, hipStream_t st) {
 hipError_t gather(const float* X, const float* Y, const float* RW, const int32_t* idx, int rows,
                   int Bp, const float* lo, const float* hi, __bf16* x0, __bf16* x0t, float* t,
                   float* rw, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3((Bp + 127) / 128), dim3(128), 0, st, X, Y, RW, idx, rows, Bp,
+  const int n = Bp * (KIN + (t ? NOUTP : 0));
+  hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, st, X, Y, RW, idx, rows, Bp,
                      lo, hi, x0, x0t, t, rw);
   return hipGetLastError();
 }

@@ -118,3 +118,51 @@ def test_batch_rejects_mixed_switches(lbm):
     with pytest.raises(lbm.LbmError) as e:
         lbm.Batch(probs)
     assert e.value.status == lbm.LBM_EINVAL
+
+
+@pytest.mark.timeout(900)
+def test_sweep_rows_graph_replay_match_oracle(lbm, oracle_mod):
+    """Six runs of the benchmark's sweep (sampler seed 0, parameters as drawn:
+    the narrowest and widest channel, the slowest and fastest reaction, the
+    longest capillary and one more) batched as the sweep runs them (graph
+    replay, fronts recorded on the device at 16 sample times of 2000 steps)
+    against the oracle: every recorded front within 0.01 lu, growth events and
+    closure steps exact; fields within the parity tolerances at step 1000 (the
+    step the contract fixes them at) and within the random-state bounds (2e-5)
+    at step 2000, where the run with the fastest reaction in a narrow channel
+    reaches 1.1e-5 in the density."""
+    from paper_1309_6726_amd import sweep
+    rows = inputs.sweep_params(0, 512)
+    pick = [int(np.argmin(rows[:, 0])), int(np.argmax(rows[:, 0])), int(np.argmin(rows[:, 2])),
+            int(np.argmax(rows[:, 2])), int(np.argmax(rows[:, 1])), 7]
+    probs = [inputs.sweep_problem(rows[i], i) for i in pick]
+    T, NS = 2000, 16
+    times = sweep.sample_times(T, NS)
+    PT.say(f"[sweep rows vs oracle] instances {pick}, sizes {[p.solid.shape for p in probs]}, "
+           f"{T} steps, graph chunk {times[0]}")
+    b = lbm.Batch(probs, nslots=NS, graph_chunk=times[0])
+    orcs = [oracle_mod.Oracle.from_problem(p) for p in probs]
+    oz = np.zeros((len(probs), NS))
+    done = 0
+    for j, t in enumerate(times):
+        b.step(t - done)
+        b.record_fronts(j)
+        for i, o in enumerate(orcs):
+            o.step(t - done)
+            oz[i, j] = o.observe()["front_z"]
+            if t == 1000:
+                PT.compare_fields(b.fields(i), o.fields(), where=f"sweep run {pick[i]} step 1000")
+        done = t
+    gz = b.fronts()
+    assert np.abs(gz - oz).max() <= PT.Z_TOL, float(np.abs(gz - oz).max())
+    nev = 0
+    for i, o in enumerate(orcs):
+        ge, oe = PT.event_set(b.events(i)), PT.event_set(o.events())
+        assert ge == oe, (pick[i], len(ge - oe), len(oe - ge))
+        nev += len(ge)
+        assert b.observe(i)["closure_step"] == o.observe()["closure_step"]
+        PT.compare_fields(b.fields(i), o.fields(), rho_tol=2e-5, u_tol=2e-5, conc_tol=2e-5,
+                          where=f"sweep run {pick[i]} step 2000")
+    PT.say(f"  fronts within {np.abs(gz - oz).max():.2e} lu, {nev} growth events identical")
+    assert nev > 0
+    b.close()
