@@ -212,13 +212,14 @@ lbm_status lbm_get_load_hint(const lbm_sim* sim, int32_t* nontemporal);
 enum { LBM_SCHEME_AUTO = 0, LBM_SCHEME_POPULATIONS = 1, LBM_SCHEME_MOMENTS = 2 };
 lbm_status lbm_set_scheme(lbm_sim* sim, int32_t scheme);
 
-/* Time the launch shapes and, with FP64 arithmetic, both load hints
- * (steps_per_candidate steps each, on a saved copy of the state, which is
- * restored), keep the fastest and report the shape (the hint is read with
- * lbm_get_load_hint).  When the environment variable LBM_AUTOTUNE_CACHE names
- * a file, a cached choice for the same (GPU architecture, nx x ny,
- * solute/reaction switches, arithmetic, scheme) is used without timing, and
- * new choices are appended to it as JSON lines
+/* Time the launch shapes and both load hints (steps_per_candidate steps
+ * each, on a saved copy of the state, which is restored), time the three
+ * fastest again, interleaved, three times over at least 20 ms each, keep the
+ * one with the lowest median and report its shape and median time per step
+ * (the hint is read with lbm_get_load_hint).  When the environment variable
+ * LBM_AUTOTUNE_CACHE names a file, a cached choice for the same (GPU
+ * architecture, nx x ny, solute/reaction switches, scheme) is used without
+ * timing, and new choices are appended to it as JSON lines
  * {"key": ..., "tx": ..., "sy": ..., "ms": ..., "nt": ...}. */
 lbm_status lbm_autotune(lbm_sim* sim, int32_t steps_per_candidate, int32_t* tx, int32_t* sy,
                         double* best_ms_per_step);
@@ -274,8 +275,9 @@ lbm_status lbm_batch_fields(lbm_batch* b, int32_t i, uint32_t field_mask, double
 lbm_status lbm_batch_events(lbm_batch* b, int32_t i, int64_t first, lbm_event* buf, int64_t cap,
                             int64_t* n);
 
-/* Before the first step only: time the launch shapes, keep the fastest and
- * reset every instance to its initial state. */
+/* Before the first step only: time the launch shapes, time the three
+ * fastest again (interleaved, three times over at least 5 ms each), keep the
+ * lowest median and reset every instance to its initial state. */
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t steps, int32_t* tx, int32_t* sy,
                               double* best_ms_per_step);
 

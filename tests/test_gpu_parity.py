@@ -232,6 +232,37 @@ def test_tile_shapes_bitwise_sweep_geometry(lbm, scheme):
             assert state == ref[0], tile
 
 
+# The launch shapes lbm_autotune times: TX 64/128/256 (64 only in the moment
+# step), SY from this list (heights beyond 2 ny skipped), both load hints.
+AUTOTUNE_SY = (6, 8, 9, 10, 12, 16, 20, 24, 28, 32, 40, 48, 64, 96, 128)
+
+
+@pytest.mark.parametrize("scheme", ["moments", "populations"])
+def test_every_autotune_candidate_bitwise(lbm, scheme):
+    """Whatever shape and load hint the autotuner picks, the run is the same
+    bit for bit (state and growth events), and a repeat of one shape too."""
+    prob = inputs.capillary_problem(300, 40, 20, seed=7, k_r=0.01, threshold=0.4, D=0.05)
+    txs = (64,) if scheme == "moments" else (64, 128, 256)
+    shapes = [(tx, sy, nt) for nt in (0, 1) for tx in txs for sy in AUTOTUNE_SY if sy <= 2 * 40]
+    shapes.append(shapes[0])  # a repeat
+    PT.say(f"[autotune candidates] {scheme}: {len(shapes)} runs of 300 steps")
+    ref = None
+    for tx, sy, nt in shapes:
+        sim = lbm.Sim.from_problem(prob, tile=(tx, sy), scheme=scheme)
+        sim.set_load_hint(nt)
+        sim.step(300)
+        blob = sim.save()
+        n_ev = int(np.frombuffer(blob[32:40], dtype=np.int64)[0])
+        state = blob[:len(blob) - n_ev * lbm.EVENT_DTYPE.itemsize]
+        ev = sorted(PT.event_set(sim.events()))
+        sim.close()
+        if ref is None:
+            ref = (state, ev)
+            assert len(ev) > 0
+        else:
+            assert ev == ref[1] and state == ref[0], (tx, sy, nt)
+
+
 @pytest.mark.parametrize("scheme", ["moments", "populations"])
 def test_load_hint_changes_no_bit(lbm, scheme):
     """The non-temporal load hint is a cache policy: same state and events."""
