@@ -365,6 +365,30 @@ def test_config2_full_domain_1000_steps_and_first_events(lbm, oracle_mod):
     assert len(ge) >= 50
 
 
+@pytest.mark.timeout(900)
+def test_population_step_preform_full_domain(lbm, oracle_mod):
+    """The population step (any tau) on the whole 2048x2048 preform at
+    tau = 0.8, in its benchmark launch shape (256x6 tiles, non-temporal
+    loads), against the oracle after 500 steps: every field, masses and
+    ledgers within the parity tolerances."""
+    prob = inputs.config2(seed=0)
+    p = prob.params.replace(tau=0.8)
+    PT.say(f"[population step] {prob.name} at tau 0.8: full domain, 500 steps")
+    sim = lbm.Sim(p, prob.solid, prob.rho1, prob.rho2, prob.conc, tile=(256, 6))
+    sim.set_load_hint(1)
+    orc = oracle_mod.Oracle(p, prob.solid, prob.rho1, prob.rho2, prob.conc)
+    o0 = orc.observe()
+    sim.step(500)
+    orc.step(500)
+    go = sim.observe()
+    d = _fields_cmp(sim, orc, "population step preform step 500", m_tol=1e-6)
+    for c in range(2):
+        assert abs(go["mass"][c] + go["mass_removed"][c] - o0["mass"][c]) <= 1e-6 * o0["mass"][c]
+    tot = go["solute"] + go["precipitate"] + go["solute_removed"]
+    assert abs(tot - o0["solute"]) <= 1e-6 * o0["solute"]
+    PT.say(f"  {d}")
+
+
 def test_edge_lattices(lbm, oracle_mod):
     """Smallest lattice, a lattice with no fluid, one without solid, a single
     component, no solute, ragged tiles."""
