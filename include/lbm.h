@@ -189,10 +189,13 @@ lbm_status lbm_set_tile(lbm_sim* sim, int32_t tx, int32_t sy);
 lbm_status lbm_get_tile(const lbm_sim* sim, int32_t* tx, int32_t* sy);
 
 /* Cache hint on the step's loads: 0 (default) the normal policy, 1 the
- * non-temporal hint.  Which is faster depends on how the lattice's footprint
- * meets the GPU's caches (on MI355X the hint gained 8% on a 2048^2 preform
- * and lost 12-21% at 1448^2 and 4096^2), so lbm_autotune chooses it along with
- * the launch shape.  It applies to the FP64 steps and changes no result bit. */
+ * non-temporal hint on the streamed state (population step: the populations;
+ * moment step: the moments of a workgroup's own rows and the solute
+ * populations, while the halo rows, which the neighbouring workgroup reads
+ * too, and the precipitate keep the normal policy).  Which is faster
+ * depends on how the lattice's footprint meets the GPU's caches, so
+ * lbm_autotune chooses it along with the launch shape.  It applies to the
+ * single-lattice steps (not the batched step) and changes no result bit. */
 lbm_status lbm_set_load_hint(lbm_sim* sim, int32_t nontemporal);
 lbm_status lbm_get_load_hint(const lbm_sim* sim, int32_t* nontemporal);
 

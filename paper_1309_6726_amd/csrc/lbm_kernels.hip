@@ -566,14 +566,15 @@ __device__ __forceinline__ R feq_m(R wr, R c, R eu) {
 // iteration's memory latency.  The summation order of every node is fixed,
 // so results do not depend on the tile shape.
 //
-// NT: the copies carry the non-temporal cache hint.  Whether it pays depends
-// on how the step's footprint meets the caches: on the 2048x2048 preform it
-// made the step ~8% faster, at 1448^2 and 4096^2 12-21% slower, and on a
-// batch of narrow channels 14% slower.  The single-lattice step therefore
-// takes it as an autotuned choice; the batched step leaves it off.
+// NT: the copies of data that only this wavefront reads in the step carry
+// the non-temporal cache hint: the moments of the tile's own rows and the
+// solute populations.  The two halo rows at each end (rows of the
+// neighbouring segments, which read them too) and the precipitate (read here
+// and rewritten by the same wavefront an iteration later) keep the normal
+// policy.  Whether the hint pays depends on how the step's footprint meets
+// the caches, so the single-lattice step takes it as an autotuned choice.
 template <bool SOLUTE, bool REACT, bool VAR, typename R, bool NT>
 __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) {
-  constexpr int CPOL = NT ? CPOL_NT : 0;
   // prefetch slots per buffer: 0..5 moments, 6..10 solute, 11..12 precipitate
   __shared__ float pf[2][13][64];
   const int t = threadIdx.x;
@@ -622,10 +623,15 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
   };
   using lds_ptr = __attribute__((address_space(3))) void*;
   // One dword per lane at byte offset voff + soff into prefetch slot
-  // (buf, slot), with the cache policy CPOL.
+  // (buf, slot), with the normal cache policy (to_lds) or the non-temporal
+  // one (to_lds_nt).
   auto to_lds = [&](__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, int buf, int slot) {
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)&pf[buf][slot][0], 4, (int)voff, (int)soff,
-                                             0, CPOL);
+                                             0, 0);
+  };
+  auto to_lds_nt = [&](__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, int buf, int slot) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)&pf[buf][slot][0], 4, (int)voff, (int)soff,
+                                             0, CPOL_NT);
   };
   // Copy row k's moments (fluid nodes of state n-1) and row k-2's solute
   // and precipitate (fluid owned nodes, precipitate only next to a wall of
@@ -640,15 +646,23 @@ __device__ __forceinline__ void mom_wave(const StepArgs& a, int strip, int seg) 
     if (k >= nrows) return;
     const bool got_m = active && !(own_k & SPREV);
     const unsigned vm = got_m ? 4u * ((unsigned)row_y(k) * (unsigned)nx + (unsigned)xc) : NONE;
+    if (NT && k >= 2 && k < nrows - 2) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) to_lds(rMin, vm, (unsigned)q * PB, buf, q);
+      for (int q = 0; q < 6; ++q) to_lds_nt(rMin, vm, (unsigned)q * PB, buf, q);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) to_lds(rMin, vm, (unsigned)q * PB, buf, q);
+    }
     if (SOLUTE && k >= 4) {
       const unsigned ownC = pkm2 & 0xFFu;
       const unsigned i = (unsigned)(ys + k - 4) * (unsigned)nx + (unsigned)xc;
       const bool got_g = owner && !(ownC & SPREV);
       const unsigned vg = got_g ? 4u * i : NONE;
 #pragma unroll
-      for (int q = 0; q < 5; ++q) to_lds(rGin, vg, (unsigned)q * PB, buf, 6 + q);
+      for (int q = 0; q < 5; ++q) {
+        if (NT) to_lds_nt(rGin, vg, (unsigned)q * PB, buf, 6 + q);
+        else to_lds(rGin, vg, (unsigned)q * PB, buf, 6 + q);
+      }
       if (REACT) {
         const bool got_p =
             owner && !(ownC & SCUR) &&
