@@ -165,11 +165,11 @@ def sweep_section(args, torch, dev):
 
 
 def surrogate_section(args, torch, dev, sweep_out):
-    """Train the MLP surrogate on batched LB runs (sampler seed 1), judge it on
+    """Train the MLP surrogate on batched LB runs (sampler seed 1), score it on
     held-out runs (seed 2) against the LB, and answer queries: network where it
     is in range and confident, LB otherwise (including 32 out-of-range ones).
-    The LB answers a query exactly (it is the judge), so the held-out error of
-    a query sent to it is 0."""
+    The LB answers a query exactly (it is the reference), so the held-out error
+    of a query sent to it is 0."""
     from paper_1309_6726_amd import surrogate as S
     T = args.sweep_steps
     rows, x, fr, cl, gen_s = S.generate(1, args.surr_train, T, device=dev)

@@ -194,7 +194,7 @@ def preform_rsa(nx: int = 2048, ny: int = 2048, seed: int = 0,
     fraction of the preform region reaches `target`; raises if that takes
     more than `max_attempts` candidates.  Candidate k draws (r, cx, cy) from
     counters 3k, 3k+1, 3k+2 of the seeded SplitMix64 stream, and candidates
-    are judged strictly in k order, so the result does not depend on `batch`
+    are tested strictly in k order, so the result does not depend on `batch`
     (0 = adapt the batch to the acceptance rate).
 
     Returns (solid uint8 (ny, nx), solid_fraction, n_disks, attempts)."""
